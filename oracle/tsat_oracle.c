@@ -1,0 +1,520 @@
+/*
+ * tsat_oracle.c -- plain, slow, FP64 reference of the gradient-guided SAT step
+ * (TurboSAT, arXiv 2511.07737).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark are the only code allowed to load this
+ * library.  The GPU path never calls it and shares no code with it.
+ *
+ * Every function is written as the definition it follows, with no blocking,
+ * fusion or reordering beyond what that definition states.  Section names
+ * refer to the paper:
+ *   - Sec. III-A "Binary Matrix Encoding": Problem Matrix P (one row per
+ *     clause, one column per literal), Assignment Matrix A (complete
+ *     assignments only: the negated literal is the complement), Result Matrix
+ *     R = PA (Eq. 1) = number of true literals per (clause, candidate), and
+ *     the Satisfiability Matrix (column minimum of R; nonzero iff the
+ *     candidate satisfies every clause).
+ *   - Sec. III-B "Differentiable Solving": binarization B(x) = clip(sign(x),0,1)
+ *     (Eq. 2), loss L = -sum_i S_i (Eq. 3), SmoothMin (Eq. 4), straight-through
+ *     estimator (identity gradient through B).
+ *   - Sec. IV-A "Gradient-based Optimization on GPU": N(0,1) initialization,
+ *     AdamW with lr 1e-1, x0.1 every 30 iterations, reset every 360
+ *     iterations, per-variable normalization by the row mean (Eq. 5) in front
+ *     of B.
+ *   - Sec. IV-B "CDCL-based Refinement on CPU": convergence at >99% satisfied
+ *     clauses, the k = max(20, 0.01% of V) most confident variables (smallest
+ *     final |gradient|), candidates dispatched by satisfied-clause count.
+ *
+ * Readings where the paper is silent or ambiguous (each also listed in the
+ * design notes of the repository):
+ *   R1  A_real is held as V x N logits theta; literal x_v takes B(theta_norm),
+ *       literal not-x_v takes 1 - B(theta_norm) (complete assignments).
+ *   R2  Eq. 5 is applied per variable over the N candidates; the mean mu is
+ *       clamped to +-1e-12 when |mu| < 1e-12 (sign kept, mu = 0 -> +1e-12).
+ *       In the clamped region the clamp is locally constant, so the backward
+ *       pass drops the d(mu)/d(theta) term there.
+ *   R3  B(0) = 0 (non-positive maps to 0), so b = [theta/mu > 0], evaluated
+ *       as a sign test.
+ *   R4  SmoothMin temperature tau is a parameter (default 1).  It is
+ *       evaluated with the exponent shifted by the column minimum, which is
+ *       the same value as Eq. 4.  A CNF with no clauses gives S_i = 0.
+ *   R5  Duplicate literals inside a clause are removed; tautologies are kept.
+ *   R6  AdamW follows PyTorch's documented decoupled form (the paper uses
+ *       PyTorch 2.2 and states no beta/eps/weight decay; defaults 0.9, 0.999,
+ *       1e-8, 1e-2).  The bias-correction step count starts at 1 and is not
+ *       reset by the learning-rate restart.
+ *   R7  lr(t) = max(lr_min, lr0 * decay^floor((t mod restart)/every)), t the
+ *       0-based iteration index.
+ *   R8  Partial extraction ranks variables by |g| where g is the gradient of
+ *       the loss with respect to theta; variables that occur in no clause are
+ *       skipped; ties go to the lower variable index.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_OOM (-3)
+
+/* ------------------------------------------------------------------------ */
+/* CNF container (oracle-private)                                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t V;       /* number of variables */
+    int64_t C;       /* number of clauses */
+    int64_t L;       /* number of literal occurrences after de-duplication */
+    int32_t K;       /* maximum clause width */
+    int64_t *off;    /* [C+1] */
+    int32_t *lit;    /* [L] signed 1-based literals */
+} ocnf;
+
+/* Parse a DIMACS literal stream (each clause terminated by 0) into clauses,
+ * removing repeated literals inside a clause (reading R5). */
+int orc_cnf_new(int32_t V, int64_t n, const int32_t *stream, void **out)
+{
+    if (!out || V < 0 || n < 0 || (n > 0 && !stream)) return ORC_E_ARG;
+    *out = NULL;
+    int64_t C = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t x = stream[j];
+        if (x == 0) { ++C; continue; }
+        int64_t a = x < 0 ? -(int64_t)x : x;
+        if (a > V) return ORC_E_ARG;
+    }
+    if (n > 0 && stream[n - 1] != 0) return ORC_E_ARG; /* unterminated clause */
+    ocnf *f = (ocnf *)calloc(1, sizeof(ocnf));
+    if (!f) return ORC_E_OOM;
+    f->V = V;
+    f->C = C;
+    f->off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    f->lit = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!f->off || !f->lit) { free(f->off); free(f->lit); free(f); return ORC_E_OOM; }
+    int64_t c = 0, L = 0, start = 0;
+    f->off[0] = 0;
+    f->K = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t x = stream[j];
+        if (x == 0) {
+            ++c;
+            f->off[c] = L;
+            int32_t w = (int32_t)(L - start);
+            if (w > f->K) f->K = w;
+            start = L;
+            continue;
+        }
+        int dup = 0;
+        for (int64_t q = start; q < L; ++q)
+            if (f->lit[q] == x) { dup = 1; break; }
+        if (!dup) f->lit[L++] = x;
+    }
+    f->L = L;
+    *out = f;
+    return ORC_OK;
+}
+
+void orc_cnf_free(void *h)
+{
+    ocnf *f = (ocnf *)h;
+    if (!f) return;
+    free(f->off);
+    free(f->lit);
+    free(f);
+}
+
+int64_t orc_cnf_num_clauses(const void *h) { return ((const ocnf *)h)->C; }
+int64_t orc_cnf_num_lits(const void *h) { return ((const ocnf *)h)->L; }
+int32_t orc_cnf_max_width(const void *h) { return ((const ocnf *)h)->K; }
+int32_t orc_cnf_num_vars(const void *h) { return ((const ocnf *)h)->V; }
+
+int orc_cnf_get(const void *h, int64_t *off, int32_t *lit)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f) return ORC_E_ARG;
+    if (off) memcpy(off, f->off, sizeof(int64_t) * (size_t)(f->C + 1));
+    if (lit) memcpy(lit, f->lit, sizeof(int32_t) * (size_t)f->L);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 5 + Eq. 2: per-variable normalization, then binarization              */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_MU_EPS 1e-12
+
+/* mode 1 ("mean"): b = B(theta / mu_v) with mu_v the mean of row v (reading
+ * R2, R3).  mode 0 ("none"): b = B(theta).  mu_out receives the clamped mean
+ * (mode 0: 1). */
+int orc_binarize(int32_t V, int32_t N, const double *theta, int32_t mode,
+                 uint8_t *b, double *mu_out)
+{
+    if (V < 0 || N <= 0 || !theta || !b) return ORC_E_ARG;
+    for (int32_t v = 0; v < V; ++v) {
+        const double *row = theta + (int64_t)v * N;
+        double mu = 1.0;
+        if (mode == 1) {
+            double s = 0.0;
+            for (int32_t i = 0; i < N; ++i) s += row[i];
+            mu = s / (double)N;
+            if (fabs(mu) < ORC_MU_EPS) mu = (mu >= 0.0) ? ORC_MU_EPS : -ORC_MU_EPS;
+        }
+        if (mu_out) mu_out[v] = mu;
+        for (int32_t i = 0; i < N; ++i) {
+            double a = (mode == 1) ? row[i] / mu : row[i];
+            /* B(x) = clip(sign(x), 0, 1): 1 for x > 0, 0 otherwise */
+            b[(int64_t)v * N + i] = (a > 0.0) ? 1 : 0;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 1: R = P A, and the exact check                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Value of literal x (signed, 1-based) for candidate i: A[x_v] = b,
+ * A[not x_v] = 1 - b (complete assignments, Sec. III-A). */
+static inline int lit_value(const uint8_t *b, int32_t N, int32_t x, int32_t i)
+{
+    int32_t v = (x > 0 ? x : -x) - 1;
+    int bv = b[(int64_t)v * N + i];
+    return x > 0 ? bv : 1 - bv;
+}
+
+/* R[c][i] = number of true literals of clause c under candidate i. */
+int orc_result_matrix(const void *h, int32_t N, const uint8_t *b, int32_t *R)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !b || !R) return ORC_E_ARG;
+    for (int64_t c = 0; c < f->C; ++c)
+        for (int32_t i = 0; i < N; ++i) {
+            int32_t r = 0;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) r += lit_value(b, N, f->lit[q], i);
+            R[c * N + i] = r;
+        }
+    return ORC_OK;
+}
+
+/* H[i][r] = #{c : R[c][i] = r}, r = 0..K. */
+int orc_histogram(const void *h, int32_t N, const uint8_t *b, int64_t *H)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !b || !H) return ORC_E_ARG;
+    int32_t K = f->K;
+    memset(H, 0, sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
+    for (int64_t c = 0; c < f->C; ++c)
+        for (int32_t i = 0; i < N; ++i) {
+            int32_t r = 0;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) r += lit_value(b, N, f->lit[q], i);
+            H[(int64_t)i * (K + 1) + r] += 1;
+        }
+    return ORC_OK;
+}
+
+/* Satisfiability Matrix (Sec. III-A): candidate i satisfies the CNF iff the
+ * column minimum of R is nonzero.  sat_count[i] = number of clauses with at
+ * least one true literal. */
+int orc_check(const void *h, int32_t N, const uint8_t *b, int64_t *sat_count, uint8_t *is_sat)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !b) return ORC_E_ARG;
+    for (int32_t i = 0; i < N; ++i) {
+        int64_t sat = 0;
+        int32_t colmin = INT32_MAX;
+        for (int64_t c = 0; c < f->C; ++c) {
+            int32_t r = 0;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) r += lit_value(b, N, f->lit[q], i);
+            if (r > 0) ++sat;
+            if (r < colmin) colmin = r;
+        }
+        if (sat_count) sat_count[i] = sat;
+        if (is_sat) is_sat[i] = (f->C == 0 || colmin > 0) ? 1 : 0;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 3 + Eq. 4: SmoothMin and the loss; dL/dR as a table over r            */
+/* ------------------------------------------------------------------------ */
+
+/* S_i = sum_c R_ci e^{-tau R_ci} / sum_c e^{-tau R_ci}, evaluated from the
+ * histogram H (R takes values 0..K) with the exponent shifted by r0 = min R
+ * (reading R4).  The derivative of S_i with respect to one entry R_ci = r is
+ * (w_r / D)(1 - tau (r - S_i)) with w_r = e^{-tau (r - r0)}, D = sum H w.
+ * table[i][r] = dS[i] * dS_i/dR_ci, i.e. dL/dR_ci for upstream gradient dS
+ * (dS == NULL means the loss of Eq. 3, dS_i = -1). */
+int orc_smoothmin(int32_t N, int32_t K, const int64_t *H, double tau, const double *dS,
+                  double *S, double *table, double *loss)
+{
+    if (N <= 0 || K < 0 || !H) return ORC_E_ARG;
+    double total = 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+        const int64_t *h = H + (int64_t)i * (K + 1);
+        int32_t r0 = -1;
+        for (int32_t r = 0; r <= K; ++r)
+            if (h[r] > 0) { r0 = r; break; }
+        double Si = 0.0, D = 0.0, num = 0.0;
+        if (r0 >= 0) {
+            for (int32_t r = 0; r <= K; ++r) {
+                double w = exp(-tau * (double)(r - r0));
+                D += (double)h[r] * w;
+                num += (double)r * (double)h[r] * w;
+            }
+            Si = num / D;
+        }
+        if (S) S[i] = Si;
+        total += Si;
+        if (table) {
+            double up = dS ? dS[i] : -1.0;
+            for (int32_t r = 0; r <= K; ++r) {
+                double t = 0.0;
+                if (r0 >= 0) {
+                    double w = exp(-tau * (double)(r - r0));
+                    t = up * (w / D) * (1.0 - tau * ((double)r - Si));
+                }
+                table[(int64_t)i * (K + 1) + r] = t;
+            }
+        }
+    }
+    if (loss) *loss = -total;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backward: dL/dA = P^T dL/dR, then the straight-through estimator          */
+/* ------------------------------------------------------------------------ */
+
+/* U[v][i] = dL/d(theta_norm)_vi.  Every clause c and literal l in c adds
+ * dL/dR_ci to dL/dA[l][i] (the transpose product); A[x_v] = B(.) passes it
+ * with +1 and A[not x_v] = 1 - B(.) with -1 (straight-through estimator). */
+int orc_adjoint(const void *h, int32_t N, const uint8_t *b, int32_t K, const double *table, double *U)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !b || !table || !U || K < f->K) return ORC_E_ARG;
+    memset(U, 0, sizeof(double) * (size_t)f->V * (size_t)N);
+    for (int64_t c = 0; c < f->C; ++c)
+        for (int32_t i = 0; i < N; ++i) {
+            int32_t r = 0;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) r += lit_value(b, N, f->lit[q], i);
+            double dR = table[(int64_t)i * (K + 1) + r];
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+                int32_t x = f->lit[q];
+                int32_t v = (x > 0 ? x : -x) - 1;
+                U[(int64_t)v * N + i] += (x > 0) ? dR : -dR;
+            }
+        }
+    return ORC_OK;
+}
+
+/* Backward of Eq. 5.  theta_norm_vi = theta_vi / mu_v, mu_v = mean_k theta_vk:
+ *   d theta_norm_vi / d theta_vk = delta_ik / mu_v - theta_vi / (N mu_v^2)
+ * so g_vk = U_vk / mu_v - (sum_i U_vi theta_vi) / (N mu_v^2).
+ * In the clamped region (reading R2) only the first term remains.
+ * mode 0: g = U. */
+int orc_norm_backward(int32_t V, int32_t N, const double *theta, int32_t mode, const double *U, double *g)
+{
+    if (V < 0 || N <= 0 || !theta || !U || !g) return ORC_E_ARG;
+    for (int32_t v = 0; v < V; ++v) {
+        const double *th = theta + (int64_t)v * N;
+        const double *u = U + (int64_t)v * N;
+        double *gv = g + (int64_t)v * N;
+        if (mode != 1) {
+            for (int32_t i = 0; i < N; ++i) gv[i] = u[i];
+            continue;
+        }
+        double s = 0.0;
+        for (int32_t i = 0; i < N; ++i) s += th[i];
+        double mu = s / (double)N;
+        int clamped = fabs(mu) < ORC_MU_EPS;
+        if (clamped) mu = (mu >= 0.0) ? ORC_MU_EPS : -ORC_MU_EPS;
+        double ut = 0.0;
+        for (int32_t i = 0; i < N; ++i) ut += u[i] * th[i];
+        for (int32_t k = 0; k < N; ++k)
+            gv[k] = clamped ? u[k] / mu : u[k] / mu - ut / ((double)N * mu * mu);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Optimizer (Sec. IV-A) -- readings R6, R7                                 */
+/* ------------------------------------------------------------------------ */
+
+double orc_lr(int64_t t, double lr0, double decay, int32_t every, int32_t restart, double lr_min)
+{
+    int64_t phase = (restart > 0) ? (t % restart) : t;
+    int64_t e = (every > 0) ? phase / every : 0;
+    double lr = lr0 * pow(decay, (double)e);
+    return lr > lr_min ? lr : lr_min;
+}
+
+/* One AdamW step over n parameters, t = 1-based step count:
+ *   theta <- theta (1 - lr wd)
+ *   m <- b1 m + (1 - b1) g ;  v <- b2 v + (1 - b2) g^2
+ *   theta <- theta - (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps) */
+void orc_adamw(int64_t n, double *theta, double *m, double *v, const double *g, double lr,
+               double b1, double b2, double eps, double wd, int64_t t)
+{
+    double bc1 = 1.0 - pow(b1, (double)t);
+    double bc2 = 1.0 - pow(b2, (double)t);
+    for (int64_t j = 0; j < n; ++j) {
+        theta[j] *= 1.0 - lr * wd;
+        m[j] = b1 * m[j] + (1.0 - b1) * g[j];
+        v[j] = b2 * v[j] + (1.0 - b2) * g[j] * g[j];
+        double denom = sqrt(v[j]) / sqrt(bc2) + eps;
+        theta[j] -= (lr / bc1) * m[j] / denom;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One iteration of the method, in the order of Sec. III-B and IV-A          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double tau, lr0, decay, lr_min, beta1, beta2, eps, weight_decay;
+    int32_t every, restart, mode, pad;
+} orc_params;
+
+/* Given theta, m, v (V x N, updated in place) and the 0-based iteration index
+ * t: binarize -> R -> SmoothMin/loss -> dL/dR -> P^T + STE -> Eq. 5 backward
+ * -> AdamW with lr(t) and bias-correction count t+1.  Optional outputs (any
+ * may be NULL): the bits used by the forward pass, H, S, loss, U and g. */
+int orc_step(const void *h, int32_t N, const orc_params *p, int64_t t, double *theta, double *m,
+             double *v, uint8_t *b_out, int64_t *H_out, double *S_out, double *loss_out,
+             double *U_out, double *g_out)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || !p || N <= 0 || !theta || !m || !v) return ORC_E_ARG;
+    int32_t V = f->V, K = f->K;
+    int64_t VN = (int64_t)V * N;
+    uint8_t *b = (uint8_t *)malloc((size_t)(VN > 0 ? VN : 1));
+    int64_t *H = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
+    double *S = (double *)malloc(sizeof(double) * (size_t)N);
+    double *table = (double *)malloc(sizeof(double) * (size_t)N * (size_t)(K + 1));
+    double *U = (double *)malloc(sizeof(double) * (size_t)(VN > 0 ? VN : 1));
+    double *g = (double *)malloc(sizeof(double) * (size_t)(VN > 0 ? VN : 1));
+    int rc = ORC_E_OOM;
+    if (!b || !H || !S || !table || !U || !g) goto done;
+    double loss = 0.0;
+    rc = orc_binarize(V, N, theta, p->mode, b, NULL);
+    if (!rc) rc = orc_histogram(h, N, b, H);
+    if (!rc) rc = orc_smoothmin(N, K, H, p->tau, NULL, S, table, &loss);
+    if (!rc) rc = orc_adjoint(h, N, b, K, table, U);
+    if (!rc) rc = orc_norm_backward(V, N, theta, p->mode, U, g);
+    if (rc) goto done;
+    if (b_out) memcpy(b_out, b, (size_t)VN);
+    if (H_out) memcpy(H_out, H, sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
+    if (S_out) memcpy(S_out, S, sizeof(double) * (size_t)N);
+    if (loss_out) *loss_out = loss;
+    if (U_out) memcpy(U_out, U, sizeof(double) * (size_t)VN);
+    if (g_out) memcpy(g_out, g, sizeof(double) * (size_t)VN);
+    orc_adamw(VN, theta, m, v, g, orc_lr(t, p->lr0, p->decay, p->every, p->restart, p->lr_min),
+              p->beta1, p->beta2, p->eps, p->weight_decay, t + 1);
+done:
+    free(b); free(H); free(S); free(table); free(U); free(g);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relaxed objective (for finite-difference pins of the gradient)            */
+/* ------------------------------------------------------------------------ */
+
+/* For a real-valued assignment x (V x N, x_vi in [0,1], not-x_v = 1 - x_v),
+ * R~_ci = sum_{l in c} value(l), S~_i = SmoothMin over the column (Eq. 4
+ * written directly, no histogram).  Returns S~ for candidate i only. */
+double orc_relaxed_S(const void *h, int32_t N, const double *x, int32_t i, double tau)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (f->C == 0) return 0.0;
+    double rmin = INFINITY;
+    for (int64_t c = 0; c < f->C; ++c) {
+        double r = 0.0;
+        for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+            int32_t l = f->lit[q];
+            int32_t v = (l > 0 ? l : -l) - 1;
+            double xv = x[(int64_t)v * N + i];
+            r += (l > 0) ? xv : 1.0 - xv;
+        }
+        if (r < rmin) rmin = r;
+    }
+    double num = 0.0, den = 0.0;
+    for (int64_t c = 0; c < f->C; ++c) {
+        double r = 0.0;
+        for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+            int32_t l = f->lit[q];
+            int32_t v = (l > 0 ? l : -l) - 1;
+            double xv = x[(int64_t)v * N + i];
+            r += (l > 0) ? xv : 1.0 - xv;
+        }
+        double w = exp(-tau * (r - rmin));
+        num += r * w;
+        den += w;
+    }
+    return num / den;
+}
+
+/* Relaxed loss L~(x) = -sum_i S~_i (Eq. 3). */
+double orc_relaxed_loss(const void *h, int32_t N, const double *x, double tau)
+{
+    double s = 0.0;
+    for (int32_t i = 0; i < N; ++i) s += orc_relaxed_S(h, N, x, i, tau);
+    return -s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Handoff (Sec. IV-B): confident partial assignments, candidate priority   */
+/* ------------------------------------------------------------------------ */
+
+/* Candidates ordered by satisfied-clause count (descending, ties: lower
+ * index).  For each of the first max_cands candidates: the k variables that
+ * occur in some clause and have the smallest |g_vi| (ties: lower v), in that
+ * order, as signed DIMACS literals of the candidate's bits b (+(v+1) for
+ * True, -(v+1) for False).  Slots beyond the number of eligible variables
+ * are 0.  Outputs: cand_ids[max_cands], lits[max_cands][k],
+ * sat_out[max_cands]. */
+int orc_extract_partial(const void *h, int32_t N, const double *g, const uint8_t *b,
+                        const int64_t *sat_count, int32_t max_cands, int32_t k,
+                        int32_t *cand_ids, int32_t *lits, int64_t *sat_out)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !g || !b || !sat_count || max_cands <= 0 || max_cands > N || k <= 0)
+        return ORC_E_ARG;
+    int32_t V = f->V;
+    uint8_t *occurs = (uint8_t *)calloc((size_t)(V > 0 ? V : 1), 1);
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    uint8_t *taken = (uint8_t *)malloc((size_t)(V > 0 ? V : 1));
+    if (!occurs || !order || !taken) { free(occurs); free(order); free(taken); return ORC_E_OOM; }
+    for (int64_t q = 0; q < f->L; ++q) occurs[(f->lit[q] > 0 ? f->lit[q] : -f->lit[q]) - 1] = 1;
+    /* selection sort of candidates: plain and obviously correct */
+    for (int32_t i = 0; i < N; ++i) order[i] = i;
+    for (int32_t a = 0; a < N; ++a) {
+        int32_t best = a;
+        for (int32_t j = a + 1; j < N; ++j) {
+            int64_t sj = sat_count[order[j]], sb = sat_count[order[best]];
+            if (sj > sb || (sj == sb && order[j] < order[best])) best = j;
+        }
+        int32_t tmp = order[a]; order[a] = order[best]; order[best] = tmp;
+    }
+    for (int32_t a = 0; a < max_cands; ++a) {
+        int32_t i = order[a];
+        cand_ids[a] = i;
+        if (sat_out) sat_out[a] = sat_count[i];
+        memset(taken, 0, (size_t)(V > 0 ? V : 1));
+        for (int32_t s = 0; s < k; ++s) {
+            int32_t pick = -1;
+            double pm = 0.0;
+            for (int32_t v = 0; v < V; ++v) {
+                if (!occurs[v] || taken[v]) continue;
+                double mag = fabs(g[(int64_t)v * N + i]);
+                if (pick < 0 || mag < pm) { pick = v; pm = mag; }
+            }
+            if (pick < 0) { lits[(int64_t)a * k + s] = 0; continue; }
+            taken[pick] = 1;
+            lits[(int64_t)a * k + s] = b[(int64_t)pick * N + i] ? (pick + 1) : -(pick + 1);
+        }
+    }
+    free(occurs); free(order); free(taken);
+    return ORC_OK;
+}
