@@ -1,0 +1,293 @@
+/*
+ * tsat.h -- C-ABI of the MI355X (gfx950) gradient-guided SAT hot path.
+ *
+ * Method: TurboSAT (Dai, Yu, Krishnamani, Khailany; arXiv 2511.07737).
+ * A CNF with V variables and C clauses is the binary Problem Matrix
+ * P in {0,1}^{C x 2V}; N candidate assignments are the columns of the
+ * Assignment Matrix A in {0,1}^{2V x N} (complete assignments: the negated
+ * literal is the complement); R = P A counts the true literals of every
+ * (clause, candidate) pair (Sec. III-A, Eq. 1).  Candidates are held as
+ * real logits theta in R^{V x N}; each iteration binarizes them after the
+ * per-variable normalization (Eq. 5, Eq. 2), evaluates R, the SmoothMin loss
+ * (Eq. 3, Eq. 4), back-propagates with the straight-through estimator and
+ * takes an AdamW step with the step-decay/restart schedule (Sec. IV-A).
+ *
+ * Conventions for every entry point:
+ *  - Return value: TSAT_OK (0) or a negative TSAT_E_* code.  No call aborts
+ *    the process.  On error, outputs are left untouched and
+ *    tsat_last_error() describes the failure (thread-local string, valid
+ *    until the next call on the same thread).
+ *  - Host pointers are owned by the caller and only read/written during the
+ *    call.  Device pointers (the *_dev calls) are owned by the caller (e.g.
+ *    torch tensors) and must stay valid until the work on the given stream
+ *    completes.  The solver owns all of its internal device memory.
+ *  - Arrays named [A][B] are row-major with B contiguous.  Candidate c of a
+ *    bit-packed row is bit (c % 64) of 64-bit word (c / 64); rows have
+ *    W = ceil(N / 64) words and pad bits are ignored on input, 0 on output.
+ *  - A solver is not internally synchronized: one host thread at a time.
+ */
+#ifndef TSAT_H
+#define TSAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSAT_OK 0
+#define TSAT_E_ARG (-1)     /* invalid argument, size or range */
+#define TSAT_E_PARSE (-2)   /* malformed DIMACS input */
+#define TSAT_E_OOM (-3)     /* host or device allocation failed */
+#define TSAT_E_HIP (-4)     /* HIP runtime error (no device, launch failure) */
+#define TSAT_E_STATE (-5)   /* call out of order (e.g. step before init) */
+#define TSAT_E_NUMERIC (-6) /* a logit or optimizer moment became NaN/Inf */
+
+#define TSAT_MODE_NONE 0 /* b = B(theta) */
+#define TSAT_MODE_MEAN 1 /* b = B(theta / mean_row(theta)), Eq. 5 then Eq. 2 */
+
+#define TSAT_MAX_WIDTH 32 /* widest clause (after de-duplication) */
+#define TSAT_MAX_STEP_N 1024 /* candidates per batch for the gradient step */
+
+typedef struct tsat_solver tsat_solver;
+
+/* Hyper-parameters.  Defaults (tsat_default_params): the paper's AdamW
+ * schedule (Sec. IV-A: lr 1e-1, x0.1 every 30 iterations, reset every 360,
+ * floor 1e-15), PyTorch's AdamW defaults for the constants the paper leaves
+ * open, SmoothMin tau = 1, Eq. 5 normalization on, convergence at 99% of the
+ * clauses (Sec. IV-B). */
+typedef struct {
+    double tau;           /* SmoothMin temperature, Eq. 4 (>= 0) */
+    double lr0;           /* initial / restart learning rate */
+    double lr_decay;      /* factor applied every decay_every iterations */
+    double lr_min;        /* floor of the learning rate */
+    double beta1, beta2;  /* AdamW moment decays */
+    double eps;           /* AdamW epsilon */
+    double weight_decay;  /* AdamW decoupled weight decay */
+    double converge_frac; /* convergence: best candidate satisfies > frac * C */
+    int32_t decay_every;  /* iterations per decay (> 0) */
+    int32_t restart_every;/* iterations per learning-rate restart (> 0) */
+    int32_t norm_mode;    /* TSAT_MODE_MEAN or TSAT_MODE_NONE */
+    int32_t k_partial;    /* partial-assignment size; <= 0: max(20, ceil(V/1e4)) */
+} tsat_params;
+
+typedef struct {
+    int32_t device;     /* HIP device ordinal */
+    int32_t reserved;
+    void* stream;       /* hipStream_t to run on; NULL: the solver creates one */
+    tsat_params params; /* defaults for tsat_step(params = NULL) */
+} tsat_config;
+
+typedef struct {
+    int64_t steps_done;           /* AdamW updates performed by this call */
+    int64_t first_sat_step;       /* first iteration whose binarized batch held a
+                                     satisfying candidate; -1 if none (since init) */
+    int64_t first_converged_step; /* first iteration with best > converge_frac*C; -1 */
+    int64_t best_sat_count;       /* satisfied clauses of the best candidate, last forward */
+    int64_t next_step;            /* 0-based index of the next iteration */
+    double loss;                  /* Eq. 3 at the last forward pass */
+    int32_t best_candidate;       /* most satisfied clauses, lowest index on ties */
+    int32_t sat_candidate;        /* first satisfying candidate, -1 if none */
+    int32_t nonfinite;            /* 1 if a value became NaN/Inf */
+    int32_t reserved;
+} tsat_report;
+
+typedef struct {
+    int32_t num_vars;
+    int32_t max_width;        /* widest clause after de-duplication */
+    int64_t num_clauses;      /* including empty clauses */
+    int64_t num_lits;         /* literal occurrences after de-duplication */
+    int64_t num_empty;        /* empty clauses (no candidate can satisfy the CNF) */
+    int64_t num_dup_removed;  /* repeated literals removed */
+    int64_t num_tautologies;  /* clauses holding both v and -v (kept) */
+    int64_t width_count[TSAT_MAX_WIDTH + 1]; /* clauses per width 0..32 */
+} tsat_cnf_info;
+
+/* ---------------------------------------------------------------- misc --- */
+
+/* Description of the last error on this thread ("" if none). */
+const char* tsat_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t tsat_version(void);
+
+/* Fill *p with the defaults listed above.  E_ARG if p is NULL. */
+int32_t tsat_default_params(tsat_params* p);
+
+/* ------------------------------------------------ host-only CNF helpers --- */
+
+/* Validate a DIMACS literal stream and describe the clause store it yields
+ * (Sec. III-A: one P row per clause, one column per literal).  lits holds
+ * num_lits signed 1-based literals, each clause terminated by 0.  Repeated
+ * literals inside a clause are removed; tautologies and empty clauses are
+ * kept.  No GPU is used.  E_ARG: |lit| > num_vars, num_vars < 1, a clause
+ * wider than TSAT_MAX_WIDTH after de-duplication, or an unterminated final
+ * clause.  OOM on allocation failure. */
+int32_t tsat_cnf_info_of(int32_t num_vars, int64_t num_lits, const int32_t* lits, tsat_cnf_info* out);
+
+/* Parse a DIMACS CNF file ("c" comment lines, one "p cnf V C" header, then
+ * clauses as 0-terminated integers).  Two-call pattern: with lits == NULL,
+ * *num_lits receives the stream length (literals plus terminators) and
+ * *num_vars the declared V; with lits != NULL and cap >= that length the
+ * stream is written.  E_PARSE: missing/duplicate header, non-integer token,
+ * literal out of range, clause count differing from the header.
+ * E_ARG: NULL outputs or cap too small. */
+int32_t tsat_dimacs_read(const char* path, int32_t* num_vars, int64_t* num_lits, int32_t* lits, int64_t cap);
+
+/* ------------------------------------------------------------- lifecycle --- */
+
+/* Create a solver on cfg->device (cfg NULL: device 0, own stream, default
+ * params).  E_HIP if the device is absent or the runtime fails. */
+int32_t tsat_create(const tsat_config* cfg, tsat_solver** out);
+
+/* Release the solver and all its device memory.  NULL-safe. */
+void tsat_destroy(tsat_solver* s);
+
+/* Load a CNF (Sec. III-A; the sparse clause store of Sec. IV-A).  lits as in
+ * tsat_cnf_info_of; the input is copied.  Builds the width-bucketed clause
+ * store (forward pass) and the per-variable occurrence store (backward
+ * pass) on the device.  Replaces any previous CNF and batch.  E_ARG as in
+ * tsat_cnf_info_of; OOM; HIP. */
+int32_t tsat_load_cnf(tsat_solver* s, int32_t num_vars, int64_t num_lits, const int32_t* lits);
+
+/* tsat_dimacs_read + tsat_load_cnf. */
+int32_t tsat_load_dimacs(tsat_solver* s, const char* path);
+
+/* Start a batch of N candidates (Sec. IV-A).  init_logits: host [V][N]
+ * float logits, or NULL for theta ~ N(0,1) drawn on the device from `seed`
+ * (Philox4x32-10 + Box-Muller).  AdamW moments and the iteration index are
+ * reset to 0, the binarized batch is computed.  E_STATE before a CNF is
+ * loaded; E_ARG for N < 1 or N > TSAT_MAX_STEP_N (the check-only call
+ * tsat_check_bits has no such limit). */
+int32_t tsat_init_batch(tsat_solver* s, int32_t N, uint64_t seed, const float* init_logits);
+
+/* --------------------------------------------------------------- solving --- */
+
+/* Run up to max_steps iterations (Sec. III-B, IV-A), each: forward R = P A
+ * on the current bits -> SmoothMin/loss -> straight-through adjoint ->
+ * Eq. 5 backward -> AdamW with lr(t) -> re-binarize.  Iteration t whose
+ * forward finds a satisfying candidate is recorded in first_sat_step; with
+ * stop_on_sat != 0 the run stops there without updating, so the current
+ * bits hold the witness.  params NULL: the solver's defaults.  Blocks until
+ * the work is done and fills *report (may be NULL).  E_STATE before
+ * tsat_init_batch; E_ARG for max_steps < 0 or invalid params; E_NUMERIC if
+ * a value became non-finite (the report is still filled). */
+int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, int32_t stop_on_sat,
+                  tsat_report* report);
+
+/* Note on norm_mode: the binarized batch is always that of the
+ * normalization mode of the last call that used it; a call whose params
+ * carry another mode re-binarizes theta with that mode first. */
+
+/* Exact check of the current binarized batch (Sec. III-A, Satisfiability
+ * Matrix): sat_counts[N] = clauses with >= 1 true literal, is_sat[N] = 1 iff
+ * every clause has one.  Either output may be NULL.  E_STATE before init. */
+int32_t tsat_check(tsat_solver* s, int64_t* sat_counts, uint8_t* is_sat);
+
+/* Stateless exact check of caller bits: packed is host [V][ceil(N/64)]
+ * uint64 (bit c%64 of word c/64 = value of the variable in candidate c).
+ * Any N >= 1 that fits in device memory.  Does not touch the batch.
+ * E_STATE before a CNF is loaded; E_ARG for N < 1 or NULL packed. */
+int32_t tsat_check_bits(tsat_solver* s, const uint64_t* packed, int32_t N, int64_t* sat_counts,
+                        uint8_t* is_sat);
+
+/* Current binarized values of candidate `cand`: vals[V] in {0,1}.
+ * E_ARG if cand is outside [0, N). */
+int32_t tsat_get_assignment(tsat_solver* s, int32_t cand, uint8_t* vals);
+
+/* First satisfying assignment found since init (vals[V]) and its candidate
+ * index in *cand.  E_STATE if none has been found. */
+int32_t tsat_get_witness(tsat_solver* s, uint8_t* vals, int32_t* cand);
+
+/* Handoff buffer for CPU CDCL refinement (Sec. IV-B).  Candidates are taken
+ * in order of satisfied clauses (descending; ties: lower index); for each of
+ * the first max_cands, the k variables with the smallest |dL/dtheta| at the
+ * current state (ties: lower variable index; variables that occur in no
+ * clause are skipped) are written as signed DIMACS literals of the
+ * candidate's current values, most confident first.  k <= 0 uses
+ * params.k_partial, whose default is max(20, ceil(V/1e4)).  Slots beyond
+ * the number of eligible variables hold 0.  Outputs: cand_ids[max_cands],
+ * lits[max_cands][k], sat_counts[max_cands] (may be NULL).  E_ARG for
+ * max_cands outside [1, N] or k > 4096; E_STATE before init. */
+int32_t tsat_extract_partial(tsat_solver* s, int32_t max_cands, int32_t k, int32_t* cand_ids, int32_t* lits,
+                             int64_t* sat_counts);
+
+/* ------------------------------------------------------- state and hooks --- */
+
+/* Number of candidates of the current batch (0 before init). */
+int32_t tsat_num_candidates(const tsat_solver* s);
+
+/* Widest clause of the loaded CNF (histogram bins are max_width + 1). */
+int32_t tsat_max_width(const tsat_solver* s);
+
+/* Replace theta (host [V][N]) keeping m, v and the iteration index; the bits
+ * are recomputed.  E_STATE before init. */
+int32_t tsat_set_logits(tsat_solver* s, const float* theta);
+
+/* Copy theta to host [V][N]. */
+int32_t tsat_get_logits(tsat_solver* s, float* theta);
+
+/* Replace the whole optimizer state: theta, m, v (host [V][N]) and the
+ * 0-based iteration index t; bits are recomputed, the SAT bookkeeping reset.
+ * m or v NULL: zeros. */
+int32_t tsat_set_state(tsat_solver* s, const float* theta, const float* m, const float* v, int64_t t);
+
+/* Copy the optimizer state out; any pointer may be NULL. */
+int32_t tsat_get_state(tsat_solver* s, float* theta, float* m, float* v, int64_t* t);
+
+/* Current binarized batch, host [V][ceil(N/64)] uint64. */
+int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed);
+
+/* Forward-only evaluation of the current bits (no update, no SAT
+ * bookkeeping): hist[N][max_width+1] uint32 = #{c : R_ci = r} (Eq. 1),
+ * S[N] (Eq. 4, FP64), *loss (Eq. 3).  Any output may be NULL. */
+int32_t tsat_eval(tsat_solver* s, const tsat_params* params, uint32_t* hist, double* S, double* loss);
+
+/* Gradients at the current state without updating: U[V][N] = dL/d(theta_norm)
+ * through the straight-through estimator (Sec. III-B), g[V][N] = dL/dtheta
+ * after the Eq. 5 backward.  Either output may be NULL. */
+int32_t tsat_get_grad(tsat_solver* s, const tsat_params* params, float* U, float* g);
+
+/* -------------------------------------------------- device-pointer API --- */
+/* For framework integration (e.g. a torch.autograd.Function).  All pointers
+ * are device memory owned by the caller; work is enqueued on `stream`
+ * (hipStream_t; NULL = the solver's stream) and the call returns without
+ * waiting.  The solver keeps scratch space sized for the largest N seen;
+ * calls on one solver must not overlap in time on different streams. */
+
+/* Pack a float assignment (device [V][N], value > 0.5 means True) into bits
+ * (device [V][ceil(N/64)] uint64). */
+int32_t tsat_pack_dev(tsat_solver* s, const float* assign, int32_t N, uint64_t* bits, void* stream);
+
+/* Forward of the differentiable layer: R = P A for the candidates in bits
+ * (device [V][ceil(N/64)]), then SmoothMin per candidate (Eq. 4).  Outputs:
+ * S[N] float (may be NULL), hist[N][max_width+1] uint32 (may be NULL). */
+int32_t tsat_fwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, float* S, uint32_t* hist,
+                     void* stream);
+
+/* Backward of the layer: given dS[N] = dLoss/dS_i, writes U[V][N] =
+ * dLoss/dA for the positive literal rows with the straight-through
+ * estimator (Sec. III-B), i.e. sum over clauses of P^T dLoss/dR with +1
+ * for x_v and -1 for not-x_v.  N <= TSAT_MAX_STEP_N. */
+int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, const float* dS, float* U,
+                     void* stream);
+
+/* ------------------------------------------------------------ profiling --- */
+
+/* Enable (1) or disable (0) per-kernel HIP-event timing inside tsat_step.
+ * While enabled, events are recorded on the solver's stream around each
+ * kernel of each iteration. */
+int32_t tsat_set_timing(tsat_solver* s, int32_t enable);
+
+/* Average device time in milliseconds per launch of each kernel over the
+ * timed iterations of the last tsat_step: ms[0] forward histogram (all width
+ * buckets), ms[1] SmoothMin/table, ms[2] fused adjoint/update/pack;
+ * *iters = iterations averaged.  E_STATE if nothing was timed. */
+int32_t tsat_get_timing(tsat_solver* s, double* ms, int32_t* iters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSAT_H */

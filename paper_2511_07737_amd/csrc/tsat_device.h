@@ -1,0 +1,106 @@
+// tsat_device.h -- argument blocks shared by the kernels and the host runtime
+// of the gradient-guided SAT library.  Internal: not part of the C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsat {
+
+// Per-solver control block in device memory.  Written by the SmoothMin kernel
+// (one block) and read by the kernels that follow it on the same stream, so a
+// run of steps needs no host round trip.
+struct Ctrl {
+    int64_t t;               // next 0-based iteration index
+    int64_t first_sat_step;  // -1 until a candidate satisfies every clause
+    int64_t first_conv_step; // -1 until the best candidate passes conv_frac * C
+    int64_t best_sat;        // satisfied clauses of the best candidate, last forward
+    int64_t updates;         // AdamW updates performed (lifetime)
+    double loss;             // Eq. 3 at the last forward
+    double lr;               // learning rate of the pending update
+    int32_t best_cand;
+    int32_t sat_cand;        // first satisfying candidate
+    int32_t stop;            // set when stop_on_sat and a satisfying candidate exists
+    int32_t stop_on_sat;
+    int32_t witness_pending; // the pending update records the satisfying candidate
+    int32_t nonfinite;       // a theta/m/v value became NaN or Inf
+    float f_decay;           // 1 - lr * weight_decay
+    float f_step;            // lr / (1 - beta1^t)
+    float f_isbc2;           // 1 / sqrt(1 - beta2^t)
+    float pad0;
+};
+
+struct FwdArgs {
+    const uint32_t* codes;  // [Cb][KW] literal indices of one width bucket
+    int64_t Cb;
+    int32_t KW;             // clause width of the bucket
+    int32_t K1;             // histogram bins (max width + 1)
+    const uint32_t* bits32; // literal rows viewed as dwords, row stride W2
+    int32_t W2;             // dwords per literal row (2 W)
+    int32_t DT;             // candidate dwords per block tile
+    int32_t CPT;            // clauses per thread
+    int32_t pad;
+    uint32_t* H;            // [Np][K1] accumulator
+    const Ctrl* ctrl;       // may be null
+};
+
+struct SminArgs {
+    uint32_t* H;        // [Np][K1] accumulator (read, optionally zeroed)
+    uint32_t* H_last;   // [Np][K1] copy including empty clauses, may be null
+    float* table;       // [K1][Np] dL/dR, may be null
+    float* S_out;       // [N] SmoothMin, may be null
+    double* S64_out;    // [N] SmoothMin in FP64, may be null
+    int64_t* sat_out;   // [N] satisfied clauses, may be null
+    const float* dS;    // [N] upstream gradient; null means -1 (Eq. 3)
+    Ctrl* ctrl;         // may be null (stateless evaluation)
+    int64_t C;          // clauses, empty ones included
+    int64_t n_empty;    // empty clauses (R = 0 for every candidate)
+    int32_t N, Np, K1;
+    int32_t zero_H;
+    int32_t update;     // schedule the AdamW update of this step
+    int32_t every, restart;
+    int32_t pad;
+    double tau, lr0, decay, lr_min, beta1, beta2, weight_decay, conv_frac;
+};
+
+struct VarArgs {
+    int32_t V, N, W, Np, K1, mode;
+    const uint32_t* occ_off;  // [V+1] word offsets into occ_data
+    const uint32_t* occ_mid;  // [V] first record of negative occurrences
+    const uint32_t* occ_data; // records: k-1, then the k-1 other literal indices
+    const uint64_t* lits_cur; // [2V][W]
+    uint64_t* lits_next;      // [2V][W]
+    const float* tbl;         // [K1][Np]
+    float* theta;
+    float* m;
+    float* v;
+    float* U_out;             // [V][N], may be null
+    float* g_out;             // [V][N] or [N][V], may be null
+    int32_t g_transposed;
+    float beta1, beta2, one_minus_beta1, one_minus_beta2, eps;
+    Ctrl* ctrl;
+    uint8_t* witness;         // [V]
+};
+
+struct SelectArgs {
+    const float* gT;        // [N][V]
+    const uint32_t* occ_off;
+    const uint64_t* lits;   // [2V][W]
+    const int32_t* order;   // candidates by priority
+    int32_t V, W, k, kpow2;
+    int32_t* lits_out;      // [nblocks][k]
+    int32_t* cand_out;      // [nblocks]
+};
+
+hipError_t launch_fwd(const FwdArgs& a, dim3 grid, hipStream_t st);
+hipError_t launch_smin(const SminArgs& a, hipStream_t st);
+hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st);
+hipError_t launch_expand(const uint64_t* bits, int64_t V, int W, int N, uint64_t* lits, hipStream_t st);
+hipError_t launch_pack(const float* assign, int V, int N, int W, uint64_t* out, int lit_rows, hipStream_t st);
+hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t st);
+hipError_t launch_rank(const int64_t* sat, int N, int32_t* order, hipStream_t st);
+hipError_t launch_select(const SelectArgs& a, int nblocks, hipStream_t st);
+
+enum { VOP_STEP = 0, VOP_GRAD = 1, VOP_ADJ = 2, VOP_BINARIZE = 3 };
+
+} // namespace tsat

@@ -1,0 +1,108 @@
+"""Helpers shared by the GPU parity tests: seeded states, oracle references and
+the error bounds the comparisons use.
+
+Tolerances follow from the arithmetic of the GPU path:
+  * bits, histograms, satisfied counts, verdicts: integer work, compared exactly;
+  * U: the GPU sums FP32-rounded dL/dR table entries in FP64, so its error is
+    at most 2^-24 of a_U = sum over occurrences of |table[R]|; the test allows
+    1e-5 * a_U (the gradient tolerance of the method's FP32 path);
+  * g (Eq. 5 backward, FP64 on the GPU): 1e-5 * a_g with
+    a_g = a_U / |mu| + sum_k |theta_k| a_U,k / (N mu^2) + |g|;
+  * AdamW (FP32 with FP64-derived scalars), given the GPU's own g: a few FP32
+    ulps of each term, allowed 2e-6 of the sum of term magnitudes.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as orc
+from paper_2511_07737_amd import gen, tsat
+
+TOL_GRAD = 1e-5
+TOL_ADAM = 2e-6
+
+
+def solver_or_skip():
+    import pytest
+
+    try:
+        return tsat.Solver()
+    except tsat.TsatError as e:
+        if e.code == tsat.E_HIP and "no HIP device" in str(e):
+            pytest.skip("no GPU visible")
+        raise
+
+
+def make_state(V, N, seed, t_moments=True, min_abs_mu=1e-3):
+    """theta ~ N(0,1) float32 with rows of tiny mean redrawn; m, v small."""
+    th = gen.normal_logits(V, N, seed)
+    g = gen.rng(seed + 77)
+    for _ in range(20):
+        mu = th.astype(np.float64).mean(axis=1)
+        bad = np.abs(mu) < min_abs_mu
+        if not bad.any():
+            break
+        th[bad] = g.standard_normal(size=(int(bad.sum()), N), dtype=np.float32)
+    if not t_moments:
+        return th, np.zeros_like(th), np.zeros_like(th)
+    m = (g.standard_normal(size=(V, N), dtype=np.float32) * 0.05).astype(np.float32)
+    v = (np.abs(g.standard_normal(size=(V, N), dtype=np.float32)) * 0.01 + 1e-6).astype(np.float32)
+    return th, m, v
+
+
+def abs_adjoint(cnf_o: orc.Cnf, b: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """a_U[v][i] = sum over clauses c containing v of |table[i][R_ci]| (error scale of U)."""
+    off, lit = cnf_o.clauses()
+    R = orc.result_matrix(cnf_o, b)  # [C][N]
+    N = b.shape[1]
+    A = np.zeros((cnf_o.V, N), dtype=np.float64)
+    if cnf_o.L == 0:
+        return A
+    cid = np.repeat(np.arange(cnf_o.C), np.diff(off))
+    var = np.abs(lit) - 1
+    vals = np.abs(table[np.arange(N)[None, :], R[cid]])  # [L][N]
+    np.add.at(A, var, vals)
+    return A
+
+
+def grad_bound(aU, theta, mu, g):
+    N = theta.shape[1]
+    th = theta.astype(np.float64)
+    mu = mu[:, None]
+    s = (np.abs(th) * aU).sum(axis=1, keepdims=True)
+    return aU / np.abs(mu) + s / (N * mu * mu) + np.abs(g)
+
+
+def sub_cnf(cnf: gen.CNF, vars0: np.ndarray) -> gen.CNF:
+    """Clauses of cnf that contain any of the 0-based variables vars0 (same V)."""
+    sel = np.zeros(cnf.num_vars, dtype=bool)
+    sel[vars0] = True
+    w = cnf.widths()
+    cid = np.repeat(np.arange(cnf.num_clauses), w)
+    hit = np.zeros(cnf.num_clauses, dtype=bool)
+    hit[cid[sel[np.abs(cnf.lits) - 1]]] = True
+    keep = np.nonzero(hit)[0]
+    clauses = [cnf.clause(c) for c in keep]
+    return gen.CNF.from_clauses(cnf.num_vars, clauses)
+
+
+def adam_reference(theta, m, v, g, t, p):
+    """Oracle AdamW on float64 copies; t is the 0-based iteration index."""
+    th = theta.astype(np.float64).copy()
+    mm = m.astype(np.float64).copy()
+    vv = v.astype(np.float64).copy()
+    lr = orc.lr(t, orc.default_params(lr0=p.lr0, decay=p.lr_decay, every=p.decay_every,
+                                      restart=p.restart_every, lr_min=p.lr_min))
+    orc.adamw(th, mm, vv, g.astype(np.float64), lr, t + 1, p.beta1, p.beta2, p.eps, p.weight_decay)
+    return th, mm, vv, lr
+
+
+def adam_bounds(theta, m, v, g, t, p, lr, v_new):
+    th = np.abs(theta.astype(np.float64))
+    g64 = g.astype(np.float64)
+    bc1 = 1 - p.beta1 ** (t + 1)
+    bc2 = 1 - p.beta2 ** (t + 1)
+    m_abs = p.beta1 * np.abs(m) + (1 - p.beta1) * np.abs(g64)
+    v_abs = p.beta2 * np.abs(v) + (1 - p.beta2) * g64 * g64
+    step = (lr / bc1) * m_abs / (np.sqrt(np.abs(v_new)) / np.sqrt(bc2) + p.eps)
+    return th * (1 - lr * p.weight_decay) + step, m_abs, v_abs
