@@ -93,6 +93,21 @@ typedef struct {
     int32_t reserved;
 } tsat_report;
 
+/* Per-instance results of a batch (tsat_get_instance_status). */
+typedef struct {
+    int64_t first_sat_step;       /* first iteration with a satisfying candidate, -1 if none */
+    int64_t first_converged_step; /* first iteration with best > converge_frac*C, -1 if none */
+    int64_t best_sat_count;       /* satisfied clauses of the best candidate, last forward */
+    int64_t num_clauses;
+    double loss;                  /* Eq. 3 of this instance at the last forward pass */
+    uint64_t start_ticks;         /* device real-time counter at the first forward pass */
+    uint64_t sat_ticks;           /* device real-time counter when first satisfied (0 if never) */
+    int32_t best_candidate;
+    int32_t sat_candidate;        /* -1 if none */
+    int32_t frozen;               /* 1: stopped on its satisfying candidate (stop_on_sat) */
+    int32_t num_vars;
+} tsat_instance_status;
+
 typedef struct {
     int32_t num_vars;
     int32_t max_width;        /* widest clause after de-duplication */
@@ -154,6 +169,24 @@ int32_t tsat_load_cnf(tsat_solver* s, int32_t num_vars, int64_t num_lits, const 
 /* tsat_dimacs_read + tsat_load_cnf. */
 int32_t tsat_load_dimacs(tsat_solver* s, const char* path);
 
+/* Load a batch of independent instances of uneven size, solved together
+ * (one launch per kernel covers all of them).  Instance j is the DIMACS
+ * stream lits[lit_offsets[j] .. lit_offsets[j+1]) over variables
+ * 1..num_vars[j]; lit_offsets has n_inst + 1 entries, lit_offsets[0] = 0.
+ * Every instance gets the same number of candidates N (tsat_init_batch);
+ * theta of the batch is [sum_j V_j][N] with instance j's rows starting at
+ * sum_{i<j} V_i.  Histograms, SmoothMin, the loss, SAT detection and (with
+ * stop_on_sat) freezing are per instance; the learning-rate schedule is
+ * shared.  E_ARG as in tsat_load_cnf, per instance. */
+int32_t tsat_load_cnf_batch(tsat_solver* s, int32_t n_inst, const int32_t* num_vars, const int64_t* lit_offsets,
+                            const int32_t* lits);
+
+/* Instances loaded (1 after tsat_load_cnf), 0 before any load. */
+int32_t tsat_num_instances(const tsat_solver* s);
+
+/* Variables of the loaded CNF (sum over the instances of a batch). */
+int32_t tsat_num_vars(const tsat_solver* s);
+
 /* Start a batch of N candidates (Sec. IV-A).  init_logits: host [V][N]
  * float logits, or NULL for theta ~ N(0,1) drawn on the device from `seed`
  * (Philox4x32-10 + Box-Muller).  AdamW moments and the iteration index are
@@ -168,9 +201,12 @@ int32_t tsat_init_batch(tsat_solver* s, int32_t N, uint64_t seed, const float* i
  * on the current bits -> SmoothMin/loss -> straight-through adjoint ->
  * Eq. 5 backward -> AdamW with lr(t) -> re-binarize.  Iteration t whose
  * forward finds a satisfying candidate is recorded in first_sat_step; with
- * stop_on_sat != 0 the run stops there without updating, so the current
- * bits hold the witness.  params NULL: the solver's defaults.  Blocks until
- * the work is done and fills *report (may be NULL).  E_STATE before
+ * stop_on_sat != 0 that instance is frozen there without updating (its
+ * bits hold the witness) and the run stops once every instance is frozen.
+ * params NULL: the solver's defaults.  Blocks until the work is done and
+ * fills *report (may be NULL); for a batch, loss and best_sat_count are
+ * summed over the instances, first_sat_step is the earliest one, the
+ * candidate fields are those of instance 0.  E_STATE before
  * tsat_init_batch; E_ARG for max_steps < 0 or invalid params; E_NUMERIC if
  * a value became non-finite (the report is still filled). */
 int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, int32_t stop_on_sat,
@@ -180,15 +216,29 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
  * normalization mode of the last call that used it; a call whose params
  * carry another mode re-binarizes theta with that mode first. */
 
+/* Replay iterations through a captured HIP graph (two iterations, one per
+ * bit-buffer parity, captured on first use and re-captured when the
+ * arguments change).  Not combined with tsat_set_timing.  Default off. */
+int32_t tsat_set_graph(tsat_solver* s, int32_t enable);
+
+/* Per-instance results for instances [first, first + count). */
+int32_t tsat_get_instance_status(tsat_solver* s, int32_t first, int32_t count, tsat_instance_status* out);
+
+/* Frequency in Hz of the device real-time counter behind start_ticks and
+ * sat_ticks. */
+int32_t tsat_device_clock_hz(tsat_solver* s, double* hz);
+
 /* Exact check of the current binarized batch (Sec. III-A, Satisfiability
- * Matrix): sat_counts[N] = clauses with >= 1 true literal, is_sat[N] = 1 iff
- * every clause has one.  Either output may be NULL.  E_STATE before init. */
+ * Matrix): sat_counts[n_inst][N] = clauses with >= 1 true literal,
+ * is_sat[n_inst][N] = 1 iff every clause of that instance has one.  Either
+ * output may be NULL.  E_STATE before init. */
 int32_t tsat_check(tsat_solver* s, int64_t* sat_counts, uint8_t* is_sat);
 
 /* Stateless exact check of caller bits: packed is host [V][ceil(N/64)]
  * uint64 (bit c%64 of word c/64 = value of the variable in candidate c).
  * Any N >= 1 that fits in device memory.  Does not touch the batch.
- * E_STATE before a CNF is loaded; E_ARG for N < 1 or NULL packed. */
+ * Outputs [n_inst][N].  E_STATE before a CNF is loaded; E_ARG for N < 1 or
+ * NULL packed. */
 int32_t tsat_check_bits(tsat_solver* s, const uint64_t* packed, int32_t N, int64_t* sat_counts,
                         uint8_t* is_sat);
 
@@ -197,8 +247,12 @@ int32_t tsat_check_bits(tsat_solver* s, const uint64_t* packed, int32_t N, int64
 int32_t tsat_get_assignment(tsat_solver* s, int32_t cand, uint8_t* vals);
 
 /* First satisfying assignment found since init (vals[V]) and its candidate
- * index in *cand.  E_STATE if none has been found. */
+ * index in *cand.  E_STATE if none has been found or more than one instance
+ * is loaded. */
 int32_t tsat_get_witness(tsat_solver* s, uint8_t* vals, int32_t* cand);
+
+/* Same for instance inst of a batch: vals[V_inst] over its own variables. */
+int32_t tsat_get_witness_instance(tsat_solver* s, int32_t inst, uint8_t* vals, int32_t* cand);
 
 /* Handoff buffer for CPU CDCL refinement (Sec. IV-B).  Candidates are taken
  * in order of satisfied clauses (descending; ties: lower index); for each of
@@ -209,7 +263,8 @@ int32_t tsat_get_witness(tsat_solver* s, uint8_t* vals, int32_t* cand);
  * params.k_partial, whose default is max(20, ceil(V/1e4)).  Slots beyond
  * the number of eligible variables hold 0.  Outputs: cand_ids[max_cands],
  * lits[max_cands][k], sat_counts[max_cands] (may be NULL).  E_ARG for
- * max_cands outside [1, N] or k > 4096; E_STATE before init. */
+ * max_cands outside [1, N] or k > 4096; E_STATE before init or with more
+ * than one instance loaded. */
 int32_t tsat_extract_partial(tsat_solver* s, int32_t max_cands, int32_t k, int32_t* cand_ids, int32_t* lits,
                              int64_t* sat_counts);
 
@@ -240,8 +295,9 @@ int32_t tsat_get_state(tsat_solver* s, float* theta, float* m, float* v, int64_t
 int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed);
 
 /* Forward-only evaluation of the current bits (no update, no SAT
- * bookkeeping): hist[N][max_width+1] uint32 = #{c : R_ci = r} (Eq. 1),
- * S[N] (Eq. 4, FP64), *loss (Eq. 3).  Any output may be NULL. */
+ * bookkeeping): hist[n_inst][N][max_width+1] uint32 = #{c : R_ci = r}
+ * (Eq. 1), S[n_inst][N] (Eq. 4, FP64), *loss (Eq. 3, summed over the
+ * instances).  Any output may be NULL. */
 int32_t tsat_eval(tsat_solver* s, const tsat_params* params, uint32_t* hist, double* S, double* loss);
 
 /* Gradients at the current state without updating: U[V][N] = dL/d(theta_norm)
@@ -252,9 +308,10 @@ int32_t tsat_get_grad(tsat_solver* s, const tsat_params* params, float* U, float
 /* -------------------------------------------------- device-pointer API --- */
 /* For framework integration (e.g. a torch.autograd.Function).  All pointers
  * are device memory owned by the caller; work is enqueued on `stream`
- * (hipStream_t; NULL = the solver's stream) and the call returns without
- * waiting.  The solver keeps scratch space sized for the largest N seen;
- * calls on one solver must not overlap in time on different streams. */
+ * (hipStream_t; NULL = the null/default stream, which is what torch reports
+ * for its default stream) and the call returns without waiting.  The solver keeps scratch space sized for the largest N seen;
+ * calls on one solver must not overlap in time on different streams.
+ * Forward and backward need a single-instance solver (E_STATE otherwise). */
 
 /* Pack a float assignment (device [V][N], value > 0.5 means True) into bits
  * (device [V][ceil(N/64)] uint64). */

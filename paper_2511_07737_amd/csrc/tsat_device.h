@@ -1,75 +1,110 @@
 // tsat_device.h -- argument blocks shared by the kernels and the host runtime
 // of the gradient-guided SAT library.  Internal: not part of the C-ABI.
+//
+// A solver holds one or more CNF instances (a batch of instances of uneven
+// size is stored block-diagonally: instance j owns a contiguous range of
+// variables and, inside every width bucket, a contiguous range of clauses).
+// Every instance has N candidates; histograms, dL/dR tables and SAT
+// bookkeeping are per instance.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace tsat {
 
-// Per-solver control block in device memory.  Written by the SmoothMin kernel
-// (one block) and read by the kernels that follow it on the same stream, so a
-// run of steps needs no host round trip.
+// Solver-wide control block in device memory.  The SmoothMin kernel writes
+// the schedule scalars of the pending update, the update kernel advances the
+// iteration index, so a run of steps (or a captured graph of them) needs no
+// host round trip.
 struct Ctrl {
-    int64_t t;               // next 0-based iteration index
+    int64_t t;          // next 0-based iteration index
+    int64_t updates;    // AdamW updates performed (lifetime)
+    double lr;          // learning rate of the pending update
+    int32_t stop;       // every instance is frozen: kernels return at entry
+    int32_t stop_on_sat;
+    int32_t n_frozen;   // instances frozen on a satisfying candidate
+    int32_t nonfinite;  // a theta/m/v value became NaN or Inf
+    float f_decay;      // 1 - lr * weight_decay
+    float f_step;       // lr / (1 - beta1^t)
+    float f_isbc2;      // 1 / sqrt(1 - beta2^t)
+    float pad0;
+};
+
+// Per-instance bookkeeping, written by the SmoothMin kernel.
+struct InstCtrl {
     int64_t first_sat_step;  // -1 until a candidate satisfies every clause
     int64_t first_conv_step; // -1 until the best candidate passes conv_frac * C
     int64_t best_sat;        // satisfied clauses of the best candidate, last forward
-    int64_t updates;         // AdamW updates performed (lifetime)
+    uint64_t start_time;     // device real-time counter at the first forward
+    uint64_t sat_time;       // device real-time counter when first satisfied
     double loss;             // Eq. 3 at the last forward
-    double lr;               // learning rate of the pending update
     int32_t best_cand;
     int32_t sat_cand;        // first satisfying candidate
-    int32_t stop;            // set when stop_on_sat and a satisfying candidate exists
-    int32_t stop_on_sat;
+    int32_t frozen;          // stop_on_sat: no further updates of this instance
     int32_t witness_pending; // the pending update records the satisfying candidate
-    int32_t nonfinite;       // a theta/m/v value became NaN or Inf
-    float f_decay;           // 1 - lr * weight_decay
-    float f_step;            // lr / (1 - beta1^t)
-    float f_isbc2;           // 1 / sqrt(1 - beta2^t)
-    float pad0;
+};
+
+// Static per-instance sizes.
+struct InstInfo {
+    int64_t C;       // clauses, empty ones included
+    int64_t n_empty; // empty clauses (R = 0 for every candidate)
+};
+
+// One forward work unit: a clause range of one instance inside one bucket.
+struct FwdUnit {
+    int32_t inst;
+    int32_t pad;
+    int64_t c0, c1;
 };
 
 struct FwdArgs {
     const uint32_t* codes;  // [Cb][KW] literal indices of one width bucket
-    int64_t Cb;
+    const FwdUnit* units;   // [gridDim.x]
     int32_t KW;             // clause width of the bucket
     int32_t K1;             // histogram bins (max width + 1)
     const uint32_t* bits32; // literal rows viewed as dwords, row stride W2
     int32_t W2;             // dwords per literal row (2 W)
+    int32_t Dn;             // dwords that hold candidates: ceil(N / 32)
     int32_t DT;             // candidate dwords per block tile
-    int32_t CPT;            // clauses per thread
-    int32_t pad;
-    uint32_t* H;            // [Np][K1] accumulator
+    int32_t CPT;            // clauses per thread (<= 255)
+    uint32_t* H;            // [n_inst][Np][K1] accumulators
+    int64_t H_stride;       // Np * K1
     const Ctrl* ctrl;       // may be null
+    const InstCtrl* ictrl;  // may be null
 };
 
 struct SminArgs {
-    uint32_t* H;        // [Np][K1] accumulator (read, optionally zeroed)
-    uint32_t* H_last;   // [Np][K1] copy including empty clauses, may be null
-    float* table;       // [K1][Np] dL/dR, may be null
-    float* S_out;       // [N] SmoothMin, may be null
-    double* S64_out;    // [N] SmoothMin in FP64, may be null
-    int64_t* sat_out;   // [N] satisfied clauses, may be null
-    const float* dS;    // [N] upstream gradient; null means -1 (Eq. 3)
-    Ctrl* ctrl;         // may be null (stateless evaluation)
-    int64_t C;          // clauses, empty ones included
-    int64_t n_empty;    // empty clauses (R = 0 for every candidate)
-    int32_t N, Np, K1;
+    uint32_t* H;            // [n_inst][Np][K1] accumulators (read, optionally zeroed)
+    uint32_t* H_last;       // [n_inst][N][K1] copy including empty clauses, may be null
+    float* table;           // [n_inst][K1][Np] dL/dR, may be null
+    float* S_out;           // [n_inst][N] SmoothMin, may be null
+    double* S64_out;        // [n_inst][N] SmoothMin in FP64, may be null
+    int64_t* sat_out;       // [n_inst][N] satisfied clauses, may be null
+    const float* dS;        // [n_inst][N] upstream gradient; null means -1 (Eq. 3)
+    Ctrl* ctrl;             // may be null (stateless evaluation)
+    InstCtrl* ictrl;        // may be null (stateless evaluation)
+    const InstInfo* info;   // [n_inst]
+    int32_t n_inst, N, Np, K1;
     int32_t zero_H;
-    int32_t update;     // schedule the AdamW update of this step
+    int32_t update;         // schedule the AdamW update of this step
     int32_t every, restart;
-    int32_t pad;
     double tau, lr0, decay, lr_min, beta1, beta2, weight_decay, conv_frac;
 };
 
 struct VarArgs {
     int32_t V, N, W, Np, K1, mode;
-    const uint32_t* occ_off;  // [V+1] word offsets into occ_data
+    int32_t pure_k;           // 2..4: every clause has this width and the records
+                              // carry no header; 0: generic records
+    int32_t group;            // records per scalar-load group in the pure kernel
+    const uint32_t* occ_off;  // [V+1] offsets into occ_data (words, or records if pure)
     const uint32_t* occ_mid;  // [V] first record of negative occurrences
-    const uint32_t* occ_data; // records: k-1, then the k-1 other literal indices
-    const uint64_t* lits_cur; // [2V][W]
+    const uint32_t* occ_data; // records: [k-1,] the other k-1 literal indices
+    const uint32_t* var_inst; // [V] instance of each variable, null for one instance
+    const uint64_t* lits_cur; // [2V][W] (+16 words of padding)
     uint64_t* lits_next;      // [2V][W]
-    const float* tbl;         // [K1][Np]
+    const double* mu_cur;     // [V] row means of theta behind lits_cur (raw, unclamped)
+    double* mu_next;          // [V] row means written with lits_next
+    const float* tbl;         // [n_inst][K1][Np]
     float* theta;
     float* m;
     float* v;
@@ -78,6 +113,7 @@ struct VarArgs {
     int32_t g_transposed;
     float beta1, beta2, one_minus_beta1, one_minus_beta2, eps;
     Ctrl* ctrl;
+    const InstCtrl* ictrl;    // may be null
     uint8_t* witness;         // [V]
 };
 
@@ -91,9 +127,10 @@ struct SelectArgs {
     int32_t* cand_out;      // [nblocks]
 };
 
-hipError_t launch_fwd(const FwdArgs& a, dim3 grid, hipStream_t st);
+hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st);
 hipError_t launch_smin(const SminArgs& a, hipStream_t st);
 hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st);
+int var_occupancy(const VarArgs& a, int op); // resident 256-thread blocks per CU of the step kernel
 hipError_t launch_expand(const uint64_t* bits, int64_t V, int W, int N, uint64_t* lits, hipStream_t st);
 hipError_t launch_pack(const float* assign, int V, int N, int W, uint64_t* out, int lit_rows, hipStream_t st);
 hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_t st);

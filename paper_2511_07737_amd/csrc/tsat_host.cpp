@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -63,6 +64,13 @@ static bool inject_alloc_failure()
     return false;
 }
 
+// launch-shape knobs, overridable from the environment for tuning sweeps
+static int env_int(const char* name, int dflt)
+{
+    const char* e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
@@ -103,8 +111,11 @@ struct DBuf {
 // host-side clause store (Sec. III-A; sparse P of Sec. IV-A)
 // ---------------------------------------------------------------------------
 
+// A batch of instances is stored block-diagonally: instance j's variables
+// are var_base[j] .. var_base[j+1]-1 of the union, and inside every width
+// bucket its clauses are the contiguous range inst_off[k][j] .. [j+1].
 struct Store {
-    int32_t V = 0;
+    int32_t V = 0;       // variables of the union
     int32_t K = 0;       // widest clause
     int64_t C = 0;       // clauses including empty ones
     int64_t L = 0;       // literal occurrences
@@ -113,64 +124,113 @@ struct Store {
     int64_t n_taut = 0;
     int64_t width_count[TSAT_MAX_WIDTH + 1] = {0};
     std::vector<std::vector<uint32_t>> buckets; // [k] -> [Cb][k] literal codes 2*var+neg
-    // occurrence store with literal codes (converted to byte offsets on upload)
+    int32_t n_inst = 1;
+    std::vector<uint32_t> var_base;                // [n_inst+1]
+    std::vector<InstInfo> info;                    // [n_inst]
+    std::vector<std::vector<int64_t>> inst_off;    // [k][n_inst+1]
+    // Occurrence store.  Generic: per variable, word offsets of records
+    // (k-1, other literal codes).  Pure (every non-empty clause of width
+    // pure_k in 2..4): record offsets of header-less records of k-1 codes.
+    int32_t pure_k = 0;
     std::vector<uint32_t> occ_off, occ_mid, occ_data;
 };
 
-static inline uint32_t lit_code(int32_t x) { return x > 0 ? 2u * (uint32_t)(x - 1) : 2u * (uint32_t)(-x - 1) + 1u; }
-
-static int32_t build_store(int32_t V, int64_t n, const int32_t* lits, Store& st, bool with_occ)
+static inline uint32_t lit_code(int32_t x, uint32_t base)
 {
-    if (V < 1) return fail(TSAT_E_ARG, "num_vars must be >= 1 (got %d)", V);
-    if (n < 0 || (n > 0 && !lits)) return fail(TSAT_E_ARG, "invalid literal stream (n=%lld)", (long long)n);
-    if (n > 0 && lits[n - 1] != 0) return fail(TSAT_E_ARG, "the last clause is not terminated by 0");
-    if ((int64_t)2 * V > (int64_t)0x7fffffff) return fail(TSAT_E_ARG, "too many variables (%d)", V);
+    return x > 0 ? 2u * (base + (uint32_t)(x - 1)) : 2u * (base + (uint32_t)(-x - 1)) + 1u;
+}
+
+// Validate n_inst DIMACS streams (instance j: lits[lit_off[j] .. lit_off[j+1]),
+// variables 1..num_vars[j]) and build the clause store of their union:
+// repeated literals inside a clause are removed, tautologies and empty
+// clauses kept, clauses bucketed by width in instance order.
+static int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_t* lit_off, const int32_t* lits,
+                           Store& st, bool with_occ)
+{
+    if (n_inst < 1 || !num_vars || !lit_off) return fail(TSAT_E_ARG, "invalid instance list");
     st = Store();
-    st.V = V;
+    st.n_inst = n_inst;
+    st.var_base.assign((size_t)n_inst + 1, 0);
+    st.info.assign((size_t)n_inst, InstInfo{0, 0});
+    int64_t total_v = 0;
+    for (int32_t j = 0; j < n_inst; ++j) {
+        if (num_vars[j] < 1) return fail(TSAT_E_ARG, "num_vars must be >= 1 (instance %d has %d)", j, num_vars[j]);
+        const int64_t n = lit_off[j + 1] - lit_off[j];
+        if (n < 0 || (n > 0 && !lits)) return fail(TSAT_E_ARG, "invalid literal stream of instance %d", j);
+        if (n > 0 && lits[lit_off[j + 1] - 1] != 0)
+            return fail(TSAT_E_ARG, "the last clause of instance %d is not terminated by 0", j);
+        st.var_base[j] = (uint32_t)total_v;
+        total_v += num_vars[j];
+        if (2 * total_v > (int64_t)0x7fffffff) return fail(TSAT_E_ARG, "too many variables (%lld)", (long long)total_v);
+    }
+    st.var_base[n_inst] = (uint32_t)total_v;
+    st.V = (int32_t)total_v;
     std::vector<uint32_t> cl;
     std::vector<std::vector<uint32_t>> buckets(TSAT_MAX_WIDTH + 1);
-    int64_t start = 0;
+    std::vector<std::vector<int64_t>> inst_cnt(TSAT_MAX_WIDTH + 1, std::vector<int64_t>((size_t)n_inst, 0));
     try {
-        for (int64_t j = 0; j < n; ++j) {
-            const int32_t x = lits[j];
-            if (x != 0) {
-                const int64_t a = x < 0 ? -(int64_t)x : (int64_t)x;
-                if (a > V) return fail(TSAT_E_ARG, "literal %d at position %lld exceeds num_vars=%d", x, (long long)j, V);
-                continue;
+        for (int32_t j = 0; j < n_inst; ++j) {
+            const uint32_t base = st.var_base[j];
+            const int32_t Vj = num_vars[j];
+            int64_t start = lit_off[j];
+            for (int64_t q = lit_off[j]; q < lit_off[j + 1]; ++q) {
+                const int32_t x = lits[q];
+                if (x != 0) {
+                    const int64_t a = x < 0 ? -(int64_t)x : (int64_t)x;
+                    if (a > Vj)
+                        return fail(TSAT_E_ARG, "literal %d at position %lld exceeds num_vars=%d", x,
+                                    (long long)(q - lit_off[j]), Vj);
+                    continue;
+                }
+                cl.clear();
+                for (int64_t e = start; e < q; ++e) cl.push_back(lit_code(lits[e], base));
+                start = q + 1;
+                std::sort(cl.begin(), cl.end());
+                const size_t before = cl.size();
+                cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+                st.n_dup += (int64_t)(before - cl.size());
+                for (size_t e = 1; e < cl.size(); ++e)
+                    if ((cl[e] >> 1) == (cl[e - 1] >> 1)) { ++st.n_taut; break; }
+                const size_t k = cl.size();
+                if (k > TSAT_MAX_WIDTH)
+                    return fail(TSAT_E_ARG, "clause %lld has %zu distinct literals (max %d)", (long long)st.C, k,
+                                TSAT_MAX_WIDTH);
+                buckets[k].insert(buckets[k].end(), cl.begin(), cl.end());
+                st.width_count[k] += 1;
+                inst_cnt[k][j] += 1;
+                st.info[j].C += 1;
+                if (k == 0) st.info[j].n_empty += 1;
+                if ((int)k > st.K) st.K = (int)k;
+                st.C += 1;
+                st.L += (int64_t)k;
             }
-            cl.clear();
-            for (int64_t q = start; q < j; ++q) cl.push_back(lit_code(lits[q]));
-            start = j + 1;
-            std::sort(cl.begin(), cl.end());
-            const size_t before = cl.size();
-            cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
-            st.n_dup += (int64_t)(before - cl.size());
-            for (size_t q = 1; q < cl.size(); ++q)
-                if ((cl[q] >> 1) == (cl[q - 1] >> 1)) { ++st.n_taut; break; }
-            const size_t k = cl.size();
-            if (k > TSAT_MAX_WIDTH)
-                return fail(TSAT_E_ARG, "clause %lld has %zu distinct literals (max %d)", (long long)st.C, k, TSAT_MAX_WIDTH);
-            buckets[k].insert(buckets[k].end(), cl.begin(), cl.end());
-            st.width_count[k] += 1;
-            if ((int)k > st.K) st.K = (int)k;
-            st.C += 1;
-            st.L += (int64_t)k;
         }
     } catch (const std::bad_alloc&) {
         return fail(TSAT_E_OOM, "host allocation failed while building the clause store");
     }
     st.n_empty = st.width_count[0];
     st.buckets = std::move(buckets);
+    st.inst_off.assign(TSAT_MAX_WIDTH + 1, std::vector<int64_t>((size_t)n_inst + 1, 0));
+    for (int k = 0; k <= TSAT_MAX_WIDTH; ++k)
+        for (int32_t j = 0; j < n_inst; ++j) st.inst_off[k][j + 1] = st.inst_off[k][j] + inst_cnt[k][j];
     if (!with_occ) return TSAT_OK;
     // per variable: records of positive occurrences, then negative ones;
-    // record = (k-1, codes of the other k-1 literals)
+    // record = (k-1, codes of the other k-1 literals), without the leading
+    // k-1 when every clause has the same width
+    {
+        int64_t nonempty = 0;
+        for (int k = 1; k <= TSAT_MAX_WIDTH; ++k) nonempty += st.width_count[k];
+        if (st.K >= 2 && st.K <= 4 && st.width_count[st.K] == nonempty) st.pure_k = st.K;
+    }
+    const bool pure = st.pure_k != 0;
+    const int32_t V = st.V;
     try {
         std::vector<uint64_t> wpos(V, 0), wneg(V, 0);
         for (int k = 1; k <= st.K; ++k) {
             const auto& b = st.buckets[k];
             for (size_t q = 0; q < b.size(); ++q) {
                 const uint32_t c = b[q];
-                (c & 1u ? wneg : wpos)[c >> 1] += (uint64_t)k;
+                (c & 1u ? wneg : wpos)[c >> 1] += pure ? 1u : (uint64_t)k;
             }
         }
         uint64_t total = 0;
@@ -183,7 +243,10 @@ static int32_t build_store(int32_t V, int64_t n, const int32_t* lits, Store& st,
             if (total > 0xffffffffull) return fail(TSAT_E_ARG, "occurrence store exceeds 2^32 words");
         }
         st.occ_off[V] = (uint32_t)total;
-        st.occ_data.assign(total, 0);
+        // pure records are counted in records; the array holds (k-1) words each
+        const uint64_t words = pure ? total * (uint64_t)(st.pure_k - 1) : total;
+        if (words > 0xffffffffull) return fail(TSAT_E_ARG, "occurrence store exceeds 2^32 words");
+        st.occ_data.assign(words, 0);
         std::vector<uint32_t> curp(V), curn(V);
         for (int32_t v = 0; v < V; ++v) {
             curp[v] = st.occ_off[v];
@@ -197,9 +260,16 @@ static int32_t build_store(int32_t V, int64_t n, const int32_t* lits, Store& st,
                 for (int e = 0; e < k; ++e) {
                     const uint32_t code = lit[e];
                     uint32_t& pos = (code & 1u) ? curn[code >> 1] : curp[code >> 1];
-                    st.occ_data[pos++] = (uint32_t)(k - 1);
-                    for (int f = 0; f < k; ++f)
-                        if (f != e) st.occ_data[pos++] = lit[f];
+                    if (pure) {
+                        size_t w = (size_t)pos * (size_t)(k - 1);
+                        for (int f = 0; f < k; ++f)
+                            if (f != e) st.occ_data[w++] = lit[f];
+                        ++pos;
+                    } else {
+                        st.occ_data[pos++] = (uint32_t)(k - 1);
+                        for (int f = 0; f < k; ++f)
+                            if (f != e) st.occ_data[pos++] = lit[f];
+                    }
                 }
             }
         }
@@ -217,6 +287,12 @@ struct Bucket {
     int32_t k;
     int64_t count;
     DBuf codes;
+    // forward work units of this bucket, per slot count (256 / DT)
+    std::map<int, std::pair<DBuf*, int>> units;
+    ~Bucket()
+    {
+        for (auto& u : units) delete u.second.first;
+    }
 };
 
 struct tsat_solver {
@@ -229,19 +305,25 @@ struct tsat_solver {
     bool loaded = false;
     Store st;
     std::vector<Bucket*> buckets;
-    DBuf occ_off, occ_mid, occ_data;
+    DBuf occ_off, occ_mid, occ_data, var_inst, info;
 
     // batch
     int32_t N = 0, W = 0, Np = 0;
     DBuf lits[2];
+    DBuf mu[2]; // FP64 row means of theta behind lits[cur] / lits[1-cur]
     int cur = 0;
     int32_t bits_mode = TSAT_MODE_MEAN; // normalization mode the current bits were computed with
     DBuf theta, m, v;
     DBuf H, H_last, table, S64, sat;
-    DBuf ctrl, ctrl_scr, witness;
+    DBuf ctrl, ictrl, ctrl_scr, witness;
     // scratch for stateless evaluations and the device-pointer API
     DBuf lits_scr, H_scr, table_scr, S64_scr, sat_scr, tmp;
     int32_t scr_Np = 0;
+
+    // graph replay of two iterations (one per buffer parity)
+    bool use_graph = false;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<char> graph_key;
 
     // timing
     bool timing = false;
@@ -249,8 +331,15 @@ struct tsat_solver {
     double timed_ms[3] = {0, 0, 0};
     int32_t timed_iters = 0;
 
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
+        graph_key.clear();
+    }
     ~tsat_solver()
     {
+        drop_graph();
         for (auto* b : buckets) delete b;
         for (auto e : events) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -275,39 +364,95 @@ static int32_t validate_params(const tsat_params* p)
     return TSAT_OK;
 }
 
-// launch geometry of the forward pass for one width bucket
-static void fwd_geometry(int32_t W2, int32_t K1, int64_t Cb, int32_t KW, int32_t& DT, int32_t& CPT, dim3& grid)
+// Forward launch geometry of one width bucket for N candidates: DT candidate
+// dwords per block (LDS bins <= 64 KiB), S = 256/DT clause slots, up to 255
+// clauses per thread (8-plane counters), units sized for ~target blocks.
+struct FwdGeom {
+    int DT, S, CPT, tiles, Dn;
+};
+
+static FwdGeom fwd_geometry(int32_t N, int32_t K1, int64_t Cb, int32_t KW)
 {
-    int bins = (KW <= 4) ? KW + 1 : K1;
-    DT = std::min(W2, 64);
-    while (DT > 1 && (size_t)DT * 32 * bins * 4 > 64 * 1024) DT >>= 1;
-    const int S = 256 / DT;
-    const int gy = (W2 + DT - 1) / DT;
-    const int64_t target_x = std::max<int64_t>(1, (2048 + gy - 1) / gy);
-    int64_t cpt = (Cb + (int64_t)S * target_x - 1) / ((int64_t)S * target_x);
-    cpt = std::max<int64_t>(16, std::min<int64_t>(255, cpt));
-    CPT = (int32_t)cpt;
-    const int64_t gx = (Cb + (int64_t)S * cpt - 1) / ((int64_t)S * cpt);
-    grid = dim3((unsigned)std::max<int64_t>(1, gx), (unsigned)gy, 1);
+    FwdGeom g;
+    const int bins = (KW <= 4) ? KW + 1 : K1;
+    g.Dn = (N + 31) / 32;
+    g.DT = std::min(g.Dn, 64);
+    while (g.DT > 1 && (size_t)g.DT * 32 * bins * 4 > 64 * 1024) g.DT >>= 1;
+    g.S = 256 / g.DT;
+    g.tiles = (g.Dn + g.DT - 1) / g.DT;
+    static const int target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", 2048));
+    const int64_t target_x = std::max<int64_t>(1, (target_blocks + g.tiles - 1) / g.tiles);
+    int64_t cpt = (Cb + (int64_t)g.S * target_x - 1) / ((int64_t)g.S * target_x);
+    g.CPT = (int)std::max<int64_t>(16, std::min<int64_t>(255, cpt));
+    return g;
 }
 
-// enqueue the forward histogram of every width bucket on literal rows `lits`
-static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t W, uint32_t* H, const Ctrl* ctrl, hipStream_t st)
+// Work units of a bucket for a slot count: per instance, clause ranges of at
+// most S * CPT clauses (a unit never spans two instances).
+static int32_t bucket_units(tsat_solver* s, Bucket* b, const FwdGeom& g, const FwdUnit** out, int* count)
+{
+    const int key = g.S * 1000 + g.CPT;
+    auto it = b->units.find(key);
+    if (it == b->units.end()) {
+        std::vector<FwdUnit> u;
+        const int64_t per = (int64_t)g.S * g.CPT;
+        const auto& off = s->st.inst_off[b->k];
+        for (int32_t j = 0; j < s->st.n_inst; ++j)
+            for (int64_t c = off[j]; c < off[j + 1]; c += per) u.push_back(FwdUnit{j, 0, c, std::min(c + per, off[j + 1])});
+        DBuf* d = new (std::nothrow) DBuf();
+        if (!d) return fail(TSAT_E_OOM, "host allocation failed");
+        int32_t rc = d->alloc(std::max<size_t>(1, u.size()) * sizeof(FwdUnit), "forward units");
+        if (rc) { delete d; return rc; }
+        if (!u.empty()) {
+            hipError_t e = hipMemcpy(d->p, u.data(), u.size() * sizeof(FwdUnit), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { delete d; return fail(TSAT_E_HIP, "unit upload: %s", hipGetErrorString(e)); }
+        }
+        it = b->units.emplace(key, std::make_pair(d, (int)u.size())).first;
+    }
+    *out = it->second.first->as<FwdUnit>();
+    *count = it->second.second;
+    return TSAT_OK;
+}
+
+// Make every bucket's unit table for N candidates resident (before a graph
+// capture, which must not allocate or copy).
+static int32_t prepare_units(tsat_solver* s, int32_t N)
 {
     for (auto* b : s->buckets) {
         if (b->count == 0 || b->k == 0) continue;
+        const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k);
+        const FwdUnit* u;
+        int n;
+        RET(bucket_units(s, b, g, &u, &n));
+    }
+    return TSAT_OK;
+}
+
+// enqueue the forward histograms of every width bucket on literal rows `lits`
+static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint32_t* H, const Ctrl* ctrl,
+                           const InstCtrl* ictrl, hipStream_t st)
+{
+    const int32_t W = (N + 63) / 64;
+    for (auto* b : s->buckets) {
+        if (b->count == 0 || b->k == 0) continue;
+        const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k);
         FwdArgs a{};
+        int nunits = 0;
+        RET(bucket_units(s, b, g, &a.units, &nunits));
+        if (nunits == 0) continue;
         a.codes = b->codes.as<uint32_t>();
-        a.Cb = b->count;
         a.KW = b->k;
         a.K1 = K1_of(s);
         a.bits32 = reinterpret_cast<const uint32_t*>(lits);
         a.W2 = 2 * W;
+        a.Dn = g.Dn;
+        a.DT = g.DT;
+        a.CPT = g.CPT;
         a.H = H;
+        a.H_stride = (int64_t)64 * W * a.K1;
         a.ctrl = ctrl;
-        dim3 grid;
-        fwd_geometry(a.W2, a.K1, a.Cb, a.KW, a.DT, a.CPT, grid);
-        HIPCHK(launch_fwd(a, grid, st));
+        a.ictrl = ictrl;
+        HIPCHK(launch_fwd(a, nunits, g.tiles, st));
     }
     return TSAT_OK;
 }
@@ -315,8 +460,8 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t W, uint
 static SminArgs smin_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t Np)
 {
     SminArgs a{};
-    a.C = s->st.C;
-    a.n_empty = s->st.n_empty;
+    a.info = s->info.as<InstInfo>();
+    a.n_inst = s->st.n_inst;
     a.N = N;
     a.Np = Np;
     a.K1 = K1_of(s);
@@ -334,10 +479,15 @@ static SminArgs smin_args(tsat_solver* s, const tsat_params& p, int32_t N, int32
     return a;
 }
 
-static int var_blocks(const tsat_solver* s, int32_t V)
+// Persistent variable-major kernels: by default as many blocks as the CUs
+// hold at the kernel's occupancy, times 4 (measured faster than exactly one
+// resident round: waves that finish early pick up the remaining blocks).
+static int var_blocks(const tsat_solver* s, int32_t V, int occ = 0)
 {
+    static const int per_cu_env = env_int("TSAT_VAR_BLOCKS_PER_CU", 0);
+    const int per_cu = per_cu_env > 0 ? per_cu_env : (occ > 0 ? 4 * occ : 32);
     const int64_t want = ((int64_t)V + 3) / 4;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)s->cus * 8));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)s->cus * per_cu));
 }
 
 static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t W, int32_t Np)
@@ -349,9 +499,13 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.Np = Np;
     a.K1 = K1_of(s);
     a.mode = p.norm_mode;
+    a.pure_k = s->st.pure_k;
+    static const int group = env_int("TSAT_PURE_GROUP", 2);
+    a.group = group;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
     a.occ_data = s->occ_data.as<uint32_t>();
+    a.var_inst = s->st.n_inst > 1 ? s->var_inst.as<uint32_t>() : nullptr;
     a.beta1 = (float)p.beta1;
     a.beta2 = (float)p.beta2;
     a.one_minus_beta1 = (float)(1.0 - p.beta1);
@@ -373,13 +527,16 @@ static int32_t ensure_scratch(tsat_solver* s, int32_t N)
 {
     const int32_t W = (N + 63) / 64, Np = 64 * W;
     const int32_t K1 = K1_of(s);
-    RET(s->lits_scr.reserve((size_t)2 * s->st.V * W * 8, "scratch literal rows"));
+    const size_t ni = (size_t)s->st.n_inst;
+    RET(s->lits_scr.reserve(((size_t)2 * s->st.V * W + 16) * 8, "scratch literal rows"));
     if (Np > s->scr_Np) {
-        RET(s->H_scr.alloc((size_t)Np * K1 * 4, "scratch histogram"));
-        HIPCHK(launch_fill_u32(s->H_scr.as<uint32_t>(), (int64_t)Np * K1, 0u, s->stream));
-        RET(s->table_scr.alloc((size_t)Np * K1 * 4, "scratch table"));
-        RET(s->S64_scr.alloc((size_t)Np * 8, "scratch S"));
-        RET(s->sat_scr.alloc((size_t)Np * 8, "scratch sat counts"));
+        RET(s->H_scr.alloc(ni * Np * K1 * 4, "scratch histogram"));
+        HIPCHK(launch_fill_u32(s->H_scr.as<uint32_t>(), (int64_t)(ni * Np * K1), 0u, s->stream));
+        // the device-pointer calls run on the caller's stream: finish the fill first
+        HIPCHK(hipStreamSynchronize(s->stream));
+        RET(s->table_scr.alloc(ni * Np * K1 * 4, "scratch table"));
+        RET(s->S64_scr.alloc(ni * Np * 8, "scratch S"));
+        RET(s->sat_scr.alloc(ni * Np * 8, "scratch sat counts"));
         s->scr_Np = Np;
     }
     return TSAT_OK;
@@ -389,11 +546,15 @@ static int32_t reset_ctrl(tsat_solver* s, int64_t t)
 {
     Ctrl c{};
     c.t = t;
-    c.first_sat_step = -1;
-    c.first_conv_step = -1;
-    c.best_cand = 0;
-    c.sat_cand = -1;
     HIPCHK(hipMemcpyAsync(s->ctrl.p, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
+    std::vector<InstCtrl> ic((size_t)s->st.n_inst);
+    for (auto& x : ic) {
+        x = InstCtrl{};
+        x.first_sat_step = -1;
+        x.first_conv_step = -1;
+        x.sat_cand = -1;
+    }
+    HIPCHK(hipMemcpyAsync(s->ictrl.p, ic.data(), ic.size() * sizeof(InstCtrl), hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return TSAT_OK;
 }
@@ -404,6 +565,7 @@ static int32_t binarize_current(tsat_solver* s, int32_t mode)
     p.norm_mode = mode;
     VarArgs a = var_args(s, p, s->N, s->W, s->Np);
     a.lits_next = s->lits[s->cur].as<uint64_t>();
+    a.mu_next = s->mu[s->cur].as<double>();
     a.theta = s->theta.as<float>();
     a.ctrl = s->ctrl.as<Ctrl>();
     HIPCHK(launch_var(a, VOP_BINARIZE, var_blocks(s, s->st.V), s->stream));
@@ -418,6 +580,14 @@ static int32_t ensure_mode(tsat_solver* s, int32_t mode)
     return binarize_current(s, mode);
 }
 
+static int32_t read_ictrl(tsat_solver* s, std::vector<InstCtrl>& out)
+{
+    out.resize((size_t)s->st.n_inst);
+    HIPCHK(hipMemcpyAsync(out.data(), s->ictrl.p, out.size() * sizeof(InstCtrl), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TSAT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
@@ -426,7 +596,7 @@ extern "C" {
 
 const char* tsat_last_error(void) { return g_err.c_str(); }
 
-int32_t tsat_version(void) { return 10000; }
+int32_t tsat_version(void) { return 10100; }
 
 int32_t tsat_default_params(tsat_params* p)
 {
@@ -451,8 +621,10 @@ int32_t tsat_cnf_info_of(int32_t num_vars, int64_t num_lits, const int32_t* lits
 {
     g_err.clear();
     if (!out) return fail(TSAT_E_ARG, "out is NULL");
+    if (num_lits < 0) return fail(TSAT_E_ARG, "invalid literal stream (n=%lld)", (long long)num_lits);
     Store st;
-    RET(build_store(num_vars, num_lits, lits, st, false));
+    const int64_t off[2] = {0, num_lits};
+    RET(build_store(1, &num_vars, off, lits, st, false));
     tsat_cnf_info info{};
     info.num_vars = st.V;
     info.max_width = st.K;
@@ -590,15 +762,10 @@ void tsat_destroy(tsat_solver* s)
     delete s;
 }
 
-int32_t tsat_load_cnf(tsat_solver* s, int32_t num_vars, int64_t num_lits, const int32_t* lits)
+static int32_t load_store(tsat_solver* s, Store&& st)
 {
-    g_err.clear();
-    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
-    RET(set_dev(s));
-    Store st;
-    RET(build_store(num_vars, num_lits, lits, st, true));
     HIPCHK(hipStreamSynchronize(s->stream));
-    // drop the previous instance and batch
+    s->drop_graph();
     for (auto* b : s->buckets) delete b;
     s->buckets.clear();
     s->loaded = false;
@@ -618,16 +785,58 @@ int32_t tsat_load_cnf(tsat_solver* s, int32_t num_vars, int64_t num_lits, const 
         RET(b->codes.alloc(codes.size() * 4, "clause store"));
         HIPCHK(hipMemcpy(b->codes.p, codes.data(), codes.size() * 4, hipMemcpyHostToDevice));
     }
-    RET(s->occ_off.alloc(((size_t)s->st.V + 1) * 4, "occurrence offsets"));
-    RET(s->occ_mid.alloc((size_t)s->st.V * 4, "occurrence offsets"));
-    HIPCHK(hipMemcpy(s->occ_off.p, s->st.occ_off.data(), ((size_t)s->st.V + 1) * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s->occ_mid.p, s->st.occ_mid.data(), (size_t)s->st.V * 4, hipMemcpyHostToDevice));
-    RET(s->occ_data.alloc(std::max<size_t>(4, s->st.occ_data.size() * 4), "occurrence records"));
-    if (!s->st.occ_data.empty())
-        HIPCHK(hipMemcpy(s->occ_data.p, s->st.occ_data.data(), s->st.occ_data.size() * 4, hipMemcpyHostToDevice));
-    RET(s->witness.alloc((size_t)s->st.V, "witness"));
+    const size_t V = (size_t)s->st.V;
+    RET(s->occ_off.alloc((V + 1) * 4, "occurrence offsets"));
+    RET(s->occ_mid.alloc(V * 4, "occurrence offsets"));
+    HIPCHK(hipMemcpy(s->occ_off.p, s->st.occ_off.data(), (V + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->occ_mid.p, s->st.occ_mid.data(), V * 4, hipMemcpyHostToDevice));
+    // 64 zero words of padding: grouped record loads near the end stay in bounds
+    const size_t occ_words = s->st.occ_data.size();
+    RET(s->occ_data.alloc((occ_words + 64) * 4, "occurrence records"));
+    HIPCHK(launch_fill_u32(s->occ_data.as<uint32_t>() + occ_words, 64, 0u, s->stream));
+    if (occ_words) HIPCHK(hipMemcpy(s->occ_data.p, s->st.occ_data.data(), occ_words * 4, hipMemcpyHostToDevice));
+    const size_t ni = (size_t)s->st.n_inst;
+    RET(s->info.alloc(ni * sizeof(InstInfo), "instance sizes"));
+    HIPCHK(hipMemcpy(s->info.p, s->st.info.data(), ni * sizeof(InstInfo), hipMemcpyHostToDevice));
+    RET(s->ictrl.alloc(ni * sizeof(InstCtrl), "instance control"));
+    if (ni > 1) {
+        std::vector<uint32_t> vi(V);
+        for (size_t j = 0; j < ni; ++j)
+            for (uint32_t v = s->st.var_base[j]; v < s->st.var_base[j + 1]; ++v) vi[v] = (uint32_t)j;
+        RET(s->var_inst.alloc(V * 4, "variable instances"));
+        HIPCHK(hipMemcpy(s->var_inst.p, vi.data(), V * 4, hipMemcpyHostToDevice));
+    }
+    RET(s->witness.alloc(V, "witness"));
+    HIPCHK(hipStreamSynchronize(s->stream));
     s->loaded = true;
     return TSAT_OK;
+}
+
+int32_t tsat_load_cnf(tsat_solver* s, int32_t num_vars, int64_t num_lits, const int32_t* lits)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (num_lits < 0) return fail(TSAT_E_ARG, "invalid literal stream (n=%lld)", (long long)num_lits);
+    RET(set_dev(s));
+    Store st;
+    const int64_t off[2] = {0, num_lits};
+    RET(build_store(1, &num_vars, off, lits, st, true));
+    return load_store(s, std::move(st));
+}
+
+int32_t tsat_load_cnf_batch(tsat_solver* s, int32_t n_inst, const int32_t* num_vars, const int64_t* lit_offsets,
+                            const int32_t* lits)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (n_inst < 1 || !num_vars || !lit_offsets) return fail(TSAT_E_ARG, "invalid instance list");
+    if (lit_offsets[0] != 0) return fail(TSAT_E_ARG, "lit_offsets[0] must be 0");
+    for (int32_t j = 0; j < n_inst; ++j)
+        if (lit_offsets[j + 1] < lit_offsets[j]) return fail(TSAT_E_ARG, "lit_offsets must be non-decreasing");
+    RET(set_dev(s));
+    Store st;
+    RET(build_store(n_inst, num_vars, lit_offsets, lits, st, true));
+    return load_store(s, std::move(st));
 }
 
 int32_t tsat_load_dimacs(tsat_solver* s, const char* path)
@@ -651,22 +860,29 @@ static int32_t alloc_batch(tsat_solver* s, int32_t N)
 {
     const int32_t W = (N + 63) / 64, Np = 64 * W, K1 = K1_of(s);
     const size_t VN = (size_t)s->st.V * N;
+    const size_t ni = (size_t)s->st.n_inst;
     if ((size_t)K1 * Np * 4 > 64 * 1024)
         return fail(TSAT_E_ARG, "(max_width+1) * 64*ceil(N/64) * 4 bytes = %zu exceeds the 64 KiB table limit",
                     (size_t)K1 * Np * 4);
     RET(check_row_offsets(s, W));
-    RET(s->lits[0].alloc((size_t)2 * s->st.V * W * 8, "literal rows"));
-    RET(s->lits[1].alloc((size_t)2 * s->st.V * W * 8, "literal rows"));
+    s->drop_graph();
+    // 16 words of padding: the variable-major kernels read whole J-word rows
+    const size_t lit_words = (size_t)2 * s->st.V * W + 16;
+    for (int b = 0; b < 2; ++b) {
+        RET(s->lits[b].alloc(lit_words * 8, "literal rows"));
+        HIPCHK(launch_fill_u32(s->lits[b].as<uint32_t>(), (int64_t)lit_words * 2, 0u, s->stream));
+        RET(s->mu[b].alloc((size_t)s->st.V * 8, "row means"));
+    }
     RET(s->theta.alloc(VN * 4, "theta"));
     RET(s->m.alloc(VN * 4, "m"));
     RET(s->v.alloc(VN * 4, "v"));
-    RET(s->H.alloc((size_t)Np * K1 * 4, "histogram"));
-    RET(s->H_last.alloc((size_t)Np * K1 * 4, "histogram"));
-    RET(s->table.alloc((size_t)Np * K1 * 4, "table"));
-    RET(s->S64.alloc((size_t)Np * 8, "S"));
-    RET(s->sat.alloc((size_t)Np * 8, "sat counts"));
-    HIPCHK(launch_fill_u32(s->H.as<uint32_t>(), (int64_t)Np * K1, 0u, s->stream));
-    HIPCHK(launch_fill_u32(s->H_last.as<uint32_t>(), (int64_t)Np * K1, 0u, s->stream));
+    RET(s->H.alloc(ni * Np * K1 * 4, "histogram"));
+    RET(s->H_last.alloc(ni * Np * K1 * 4, "histogram"));
+    RET(s->table.alloc(ni * Np * K1 * 4, "table"));
+    RET(s->S64.alloc(ni * Np * 8, "S"));
+    RET(s->sat.alloc(ni * Np * 8, "sat counts"));
+    HIPCHK(launch_fill_u32(s->H.as<uint32_t>(), (int64_t)(ni * Np * K1), 0u, s->stream));
+    HIPCHK(launch_fill_u32(s->H_last.as<uint32_t>(), (int64_t)(ni * Np * K1), 0u, s->stream));
     HIPCHK(launch_fill_u32(s->m.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
     HIPCHK(launch_fill_u32(s->v.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
     s->N = N;
@@ -702,6 +918,31 @@ static int32_t need_batch(tsat_solver* s)
     return set_dev(s);
 }
 
+static int32_t need_single(tsat_solver* s)
+{
+    if (s->st.n_inst != 1) return fail(TSAT_E_STATE, "this call needs a single-instance solver (%d instances loaded)", s->st.n_inst);
+    return TSAT_OK;
+}
+
+// Enqueue one iteration (forward of all buckets -> SmoothMin -> fused update)
+// on literal buffer parity `cur`.
+static int32_t enqueue_iteration(tsat_solver* s, const SminArgs& sa, VarArgs va, int vblocks, int cur, bool timing, int it)
+{
+    Ctrl* ctrl = s->ctrl.as<Ctrl>();
+    InstCtrl* ictrl = s->ictrl.as<InstCtrl>();
+    RET(enqueue_fwd(s, s->lits[cur].as<uint64_t>(), s->N, s->H.as<uint32_t>(), ctrl, ictrl, s->stream));
+    if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 1], s->stream));
+    HIPCHK(launch_smin(sa, s->stream));
+    if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 2], s->stream));
+    va.lits_cur = s->lits[cur].as<uint64_t>();
+    va.lits_next = s->lits[1 - cur].as<uint64_t>();
+    va.mu_cur = s->mu[cur].as<double>();
+    va.mu_next = s->mu[1 - cur].as<double>();
+    HIPCHK(launch_var(va, VOP_STEP, vblocks, s->stream));
+    if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 3], s->stream));
+    return TSAT_OK;
+}
+
 int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, int32_t stop_on_sat, tsat_report* report)
 {
     g_err.clear();
@@ -727,6 +968,7 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
     sa.S64_out = s->S64.as<double>();
     sa.sat_out = s->sat.as<int64_t>();
     sa.ctrl = ctrl;
+    sa.ictrl = s->ictrl.as<InstCtrl>();
     sa.update = 1;
     VarArgs va = var_args(s, p, s->N, s->W, s->Np);
     va.tbl = s->table.as<float>();
@@ -734,9 +976,12 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
     va.m = s->m.as<float>();
     va.v = s->v.as<float>();
     va.ctrl = ctrl;
+    va.ictrl = s->ictrl.as<InstCtrl>();
     va.witness = s->witness.as<uint8_t>();
-    const int vblocks = var_blocks(s, s->st.V);
+    const int vblocks = var_blocks(s, s->st.V, var_occupancy(va, VOP_STEP));
+    RET(prepare_units(s, s->N));
 
+    const bool graph = s->use_graph && !s->timing;
     const bool timing = s->timing && max_steps > 0;
     if (timing) {
         const size_t need = (size_t)3 * max_steps + 1;
@@ -748,16 +993,43 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
         HIPCHK(hipEventRecord(s->events[0], s->stream));
     }
     int32_t executed = 0;
-    for (int32_t it = 0; it < max_steps; ++it) {
+    if (graph && max_steps >= 2) {
+        // capture two iterations (both buffer parities) once per argument set
+        std::vector<char> key(sizeof sa + sizeof va + sizeof(int) * 2);
+        memcpy(key.data(), &sa, sizeof sa);
+        memcpy(key.data() + sizeof sa, &va, sizeof va);
+        memcpy(key.data() + sizeof sa + sizeof va, &vblocks, sizeof(int));
+        memcpy(key.data() + sizeof sa + sizeof va + sizeof(int), &s->cur, sizeof(int));
+        if (!s->graph_exec || key != s->graph_key) {
+            s->drop_graph();
+            hipGraph_t g;
+            HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+            int32_t rc = enqueue_iteration(s, sa, va, vblocks, s->cur, false, 0);
+            if (!rc) rc = enqueue_iteration(s, sa, va, vblocks, 1 - s->cur, false, 0);
+            hipError_t e = hipStreamEndCapture(s->stream, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(TSAT_E_HIP, "graph capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                s->graph_exec = nullptr;
+                return fail(TSAT_E_HIP, "graph instantiation: %s", hipGetErrorString(e));
+            }
+            s->graph_key = key;
+        }
+        while (executed + 2 <= max_steps) {
+            HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
+            executed += 2;
+            if (stop_on_sat && (executed % 16) == 0 && executed < max_steps) {
+                HIPCHK(hipMemcpyAsync(&host, ctrl, sizeof host, hipMemcpyDeviceToHost, s->stream));
+                HIPCHK(hipStreamSynchronize(s->stream));
+                if (host.stop) break;
+            }
+        }
+    }
+    for (int32_t it = executed; it < max_steps; ++it) {
         ++executed;
-        RET(enqueue_fwd(s, s->lits[s->cur].as<uint64_t>(), s->W, s->H.as<uint32_t>(), ctrl, s->stream));
-        if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 1], s->stream));
-        HIPCHK(launch_smin(sa, s->stream));
-        if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 2], s->stream));
-        va.lits_cur = s->lits[s->cur].as<uint64_t>();
-        va.lits_next = s->lits[1 - s->cur].as<uint64_t>();
-        HIPCHK(launch_var(va, VOP_STEP, vblocks, s->stream));
-        if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 3], s->stream));
+        RET(enqueue_iteration(s, sa, va, vblocks, s->cur, timing, it));
         s->cur = 1 - s->cur;
         if (stop_on_sat && (it % 16) == 15 && it + 1 < max_steps) {
             HIPCHK(hipMemcpyAsync(&host, ctrl, sizeof host, hipMemcpyDeviceToHost, s->stream));
@@ -783,19 +1055,75 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
         s->timed_iters = n;
     }
     if (report) {
+        std::vector<InstCtrl> ic;
+        RET(read_ictrl(s, ic));
         tsat_report r{};
         r.steps_done = host.updates - updates0;
-        r.first_sat_step = host.first_sat_step;
-        r.first_converged_step = host.first_conv_step;
-        r.best_sat_count = host.best_sat;
         r.next_step = host.t;
-        r.loss = host.loss;
-        r.best_candidate = host.best_cand;
-        r.sat_candidate = host.sat_cand;
         r.nonfinite = host.nonfinite;
+        r.first_sat_step = -1;
+        r.first_converged_step = -1;
+        r.sat_candidate = ic[0].sat_cand;
+        r.best_candidate = ic[0].best_cand;
+        for (const auto& x : ic) {
+            r.loss += x.loss;
+            r.best_sat_count += x.best_sat;
+            if (x.first_sat_step >= 0 && (r.first_sat_step < 0 || x.first_sat_step < r.first_sat_step))
+                r.first_sat_step = x.first_sat_step;
+            if (x.first_conv_step >= 0 && (r.first_converged_step < 0 || x.first_conv_step < r.first_converged_step))
+                r.first_converged_step = x.first_conv_step;
+        }
         *report = r;
     }
     if (host.nonfinite) return fail(TSAT_E_NUMERIC, "a logit or optimizer moment became non-finite");
+    return TSAT_OK;
+}
+
+int32_t tsat_set_graph(tsat_solver* s, int32_t enable)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    s->use_graph = enable != 0;
+    if (!s->use_graph) s->drop_graph();
+    return TSAT_OK;
+}
+
+int32_t tsat_num_instances(const tsat_solver* s) { return (s && s->loaded) ? s->st.n_inst : 0; }
+
+int32_t tsat_get_instance_status(tsat_solver* s, int32_t first, int32_t count, tsat_instance_status* out)
+{
+    g_err.clear();
+    RET(need_batch(s));
+    if (first < 0 || count < 0 || first + count > s->st.n_inst || (count > 0 && !out))
+        return fail(TSAT_E_ARG, "instance range [%d, %d) outside [0, %d)", first, first + count, s->st.n_inst);
+    std::vector<InstCtrl> ic;
+    RET(read_ictrl(s, ic));
+    for (int32_t j = 0; j < count; ++j) {
+        const InstCtrl& x = ic[(size_t)(first + j)];
+        tsat_instance_status o{};
+        o.first_sat_step = x.first_sat_step;
+        o.first_converged_step = x.first_conv_step;
+        o.best_sat_count = x.best_sat;
+        o.num_clauses = s->st.info[(size_t)(first + j)].C;
+        o.loss = x.loss;
+        o.start_ticks = x.start_time;
+        o.sat_ticks = x.sat_time;
+        o.best_candidate = x.best_cand;
+        o.sat_candidate = x.sat_cand;
+        o.frozen = x.frozen;
+        o.num_vars = (int32_t)(s->st.var_base[(size_t)(first + j) + 1] - s->st.var_base[(size_t)(first + j)]);
+        out[j] = o;
+    }
+    return TSAT_OK;
+}
+
+int32_t tsat_device_clock_hz(tsat_solver* s, double* hz)
+{
+    g_err.clear();
+    if (!s || !hz) return fail(TSAT_E_ARG, "NULL argument");
+    int khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
+    *hz = 1e3 * (double)khz;
     return TSAT_OK;
 }
 
@@ -804,7 +1132,7 @@ static int32_t eval_rows(tsat_solver* s, const tsat_params& p, const uint64_t* l
                          uint32_t* H_out, float* S32, double* S64, int64_t* sat, float* table, hipStream_t st)
 {
     const int32_t W = (N + 63) / 64, Np = 64 * W;
-    RET(enqueue_fwd(s, lits, W, s->H_scr.as<uint32_t>(), nullptr, st));
+    RET(enqueue_fwd(s, lits, N, s->H_scr.as<uint32_t>(), nullptr, nullptr, st));
     SminArgs a = smin_args(s, p, N, Np);
     a.H = s->H_scr.as<uint32_t>();
     a.H_last = H_out;
@@ -813,9 +1141,28 @@ static int32_t eval_rows(tsat_solver* s, const tsat_params& p, const uint64_t* l
     a.S64_out = S64;
     a.sat_out = sat;
     a.dS = dS;
-    a.ctrl = s->ctrl_scr.as<Ctrl>();
     a.update = 0;
     HIPCHK(launch_smin(a, st));
+    return TSAT_OK;
+}
+
+static int32_t copy_sat(tsat_solver* s, int32_t N, int64_t* sat_counts, uint8_t* is_sat)
+{
+    const size_t ni = (size_t)s->st.n_inst;
+    std::vector<int64_t> sat;
+    try {
+        sat.resize(ni * (size_t)N);
+    } catch (const std::bad_alloc&) {
+        return fail(TSAT_E_OOM, "host allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(sat.data(), s->sat_scr.p, sat.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t j = 0; j < ni; ++j)
+        for (int32_t i = 0; i < N; ++i) {
+            const size_t e = j * (size_t)N + (size_t)i;
+            if (sat_counts) sat_counts[e] = sat[e];
+            if (is_sat) is_sat[e] = sat[e] == s->st.info[j].C ? 1 : 0;
+        }
     return TSAT_OK;
 }
 
@@ -826,14 +1173,7 @@ int32_t tsat_check(tsat_solver* s, int64_t* sat_counts, uint8_t* is_sat)
     RET(ensure_scratch(s, s->N));
     RET(eval_rows(s, s->params, s->lits[s->cur].as<uint64_t>(), s->N, nullptr, nullptr, nullptr, nullptr,
                   s->sat_scr.as<int64_t>(), nullptr, s->stream));
-    std::vector<int64_t> sat(s->N);
-    HIPCHK(hipMemcpyAsync(sat.data(), s->sat_scr.p, (size_t)s->N * 8, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    for (int32_t i = 0; i < s->N; ++i) {
-        if (sat_counts) sat_counts[i] = sat[i];
-        if (is_sat) is_sat[i] = sat[i] == s->st.C ? 1 : 0;
-    }
-    return TSAT_OK;
+    return copy_sat(s, s->N, sat_counts, is_sat);
 }
 
 int32_t tsat_check_bits(tsat_solver* s, const uint64_t* packed, int32_t N, int64_t* sat_counts, uint8_t* is_sat)
@@ -844,7 +1184,7 @@ int32_t tsat_check_bits(tsat_solver* s, const uint64_t* packed, int32_t N, int64
     if (N < 1 || !packed) return fail(TSAT_E_ARG, "N must be >= 1 and packed non-NULL");
     RET(set_dev(s));
     const int32_t W = (N + 63) / 64;
-    if ((size_t)K1_of(s) * 64 * W * 4 > (size_t)1 << 34) return fail(TSAT_E_ARG, "N too large");
+    if ((size_t)s->st.n_inst * K1_of(s) * 64 * W * 4 > (size_t)1 << 34) return fail(TSAT_E_ARG, "N too large");
     RET(ensure_scratch(s, N));
     const size_t vb = (size_t)s->st.V * W * 8;
     RET(s->tmp.reserve(vb, "packed input"));
@@ -852,19 +1192,7 @@ int32_t tsat_check_bits(tsat_solver* s, const uint64_t* packed, int32_t N, int64
     HIPCHK(launch_expand(s->tmp.as<uint64_t>(), s->st.V, W, N, s->lits_scr.as<uint64_t>(), s->stream));
     RET(eval_rows(s, s->params, s->lits_scr.as<uint64_t>(), N, nullptr, nullptr, nullptr, nullptr, s->sat_scr.as<int64_t>(),
                   nullptr, s->stream));
-    std::vector<int64_t> sat;
-    try {
-        sat.resize(N);
-    } catch (const std::bad_alloc&) {
-        return fail(TSAT_E_OOM, "host allocation failed");
-    }
-    HIPCHK(hipMemcpyAsync(sat.data(), s->sat_scr.p, (size_t)N * 8, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    for (int32_t i = 0; i < N; ++i) {
-        if (sat_counts) sat_counts[i] = sat[i];
-        if (is_sat) is_sat[i] = sat[i] == s->st.C ? 1 : 0;
-    }
-    return TSAT_OK;
+    return copy_sat(s, N, sat_counts, is_sat);
 }
 
 int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed)
@@ -879,16 +1207,43 @@ int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed)
     return TSAT_OK;
 }
 
+static int32_t column_values(tsat_solver* s, int32_t cand, uint32_t v0, uint32_t v1, uint8_t* vals)
+{
+    const size_t n = v1 - v0;
+    std::vector<uint64_t> col(n);
+    if (n) {
+        HIPCHK(hipMemcpy2DAsync(col.data(), 8, s->lits[s->cur].as<uint64_t>() + (size_t)2 * v0 * s->W + (cand >> 6),
+                                (size_t)2 * s->W * 8, 8, n, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    for (size_t v = 0; v < n; ++v) vals[v] = (uint8_t)((col[v] >> (cand & 63)) & 1u);
+    return TSAT_OK;
+}
+
 int32_t tsat_get_assignment(tsat_solver* s, int32_t cand, uint8_t* vals)
 {
     g_err.clear();
     RET(need_batch(s));
     if (cand < 0 || cand >= s->N || !vals) return fail(TSAT_E_ARG, "candidate %d outside [0, %d) or NULL output", cand, s->N);
-    std::vector<uint64_t> col(s->st.V);
-    HIPCHK(hipMemcpy2DAsync(col.data(), 8, s->lits[s->cur].as<uint64_t>() + (cand >> 6), (size_t)2 * s->W * 8, 8, s->st.V,
-                            hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    for (int32_t v = 0; v < s->st.V; ++v) vals[v] = (uint8_t)((col[v] >> (cand & 63)) & 1u);
+    return column_values(s, cand, 0, (uint32_t)s->st.V, vals);
+}
+
+int32_t tsat_get_witness_instance(tsat_solver* s, int32_t inst, uint8_t* vals, int32_t* cand)
+{
+    g_err.clear();
+    RET(need_batch(s));
+    if (inst < 0 || inst >= s->st.n_inst) return fail(TSAT_E_ARG, "instance %d outside [0, %d)", inst, s->st.n_inst);
+    std::vector<InstCtrl> ic;
+    RET(read_ictrl(s, ic));
+    const InstCtrl& x = ic[(size_t)inst];
+    if (x.sat_cand < 0) return fail(TSAT_E_STATE, "no satisfying assignment found yet for instance %d", inst);
+    if (cand) *cand = x.sat_cand;
+    if (!vals) return TSAT_OK;
+    const uint32_t v0 = s->st.var_base[(size_t)inst], v1 = s->st.var_base[(size_t)inst + 1];
+    // a frozen instance still holds the satisfying candidate; otherwise the
+    // update of the step that found it recorded it
+    if (x.frozen) return column_values(s, x.sat_cand, v0, v1, vals);
+    HIPCHK(hipMemcpy(vals, s->witness.as<uint8_t>() + v0, v1 - v0, hipMemcpyDeviceToHost));
     return TSAT_OK;
 }
 
@@ -896,20 +1251,15 @@ int32_t tsat_get_witness(tsat_solver* s, uint8_t* vals, int32_t* cand)
 {
     g_err.clear();
     RET(need_batch(s));
-    Ctrl host{};
-    HIPCHK(hipMemcpyAsync(&host, s->ctrl.p, sizeof host, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    if (host.sat_cand < 0) return fail(TSAT_E_STATE, "no satisfying assignment found yet");
-    if (cand) *cand = host.sat_cand;
-    if (!vals) return TSAT_OK;
-    if (host.stop) return tsat_get_assignment(s, host.sat_cand, vals);
-    HIPCHK(hipMemcpy(vals, s->witness.p, (size_t)s->st.V, hipMemcpyDeviceToHost));
-    return TSAT_OK;
+    RET(need_single(s));
+    return tsat_get_witness_instance(s, 0, vals, cand);
 }
 
 int32_t tsat_num_candidates(const tsat_solver* s) { return s ? s->N : 0; }
 
 int32_t tsat_max_width(const tsat_solver* s) { return (s && s->loaded) ? s->st.K : 0; }
+
+int32_t tsat_num_vars(const tsat_solver* s) { return (s && s->loaded) ? s->st.V : 0; }
 
 int32_t tsat_set_logits(tsat_solver* s, const float* theta)
 {
@@ -964,17 +1314,21 @@ int32_t tsat_eval(tsat_solver* s, const tsat_params* params, uint32_t* hist, dou
     RET(ensure_mode(s, p.norm_mode));
     RET(ensure_scratch(s, s->N));
     const int32_t K1 = K1_of(s);
-    RET(s->tmp.reserve((size_t)s->Np * K1 * 4, "histogram copy"));
+    const size_t ni = (size_t)s->st.n_inst;
+    RET(s->tmp.reserve(ni * s->N * K1 * 4, "histogram copy"));
     RET(eval_rows(s, p, s->lits[s->cur].as<uint64_t>(), s->N, nullptr, s->tmp.as<uint32_t>(), nullptr,
                   s->S64_scr.as<double>(), nullptr, nullptr, s->stream));
-    std::vector<double> S64(s->N);
-    HIPCHK(hipMemcpyAsync(S64.data(), s->S64_scr.p, (size_t)s->N * 8, hipMemcpyDeviceToHost, s->stream));
-    if (hist) HIPCHK(hipMemcpyAsync(hist, s->tmp.p, (size_t)s->N * K1 * 4, hipMemcpyDeviceToHost, s->stream));
-    Ctrl host{};
-    HIPCHK(hipMemcpyAsync(&host, s->ctrl_scr.p, sizeof host, hipMemcpyDeviceToHost, s->stream));
+    std::vector<double> S64(ni * s->N);
+    HIPCHK(hipMemcpyAsync(S64.data(), s->S64_scr.p, S64.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    if (hist) HIPCHK(hipMemcpyAsync(hist, s->tmp.p, ni * s->N * K1 * 4, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    if (S) memcpy(S, S64.data(), (size_t)s->N * 8);
-    if (loss) *loss = host.loss;
+    if (S) memcpy(S, S64.data(), S64.size() * 8);
+    if (loss) {
+        // Eq. 3, summed over the candidates of every instance in index order
+        double l = 0.0;
+        for (double x : S64) l -= x;
+        *loss = l;
+    }
     return TSAT_OK;
 }
 
@@ -994,6 +1348,7 @@ int32_t tsat_get_grad(tsat_solver* s, const tsat_params* params, float* U, float
     va.tbl = s->table_scr.as<float>();
     va.theta = s->theta.as<float>();
     va.lits_cur = s->lits[s->cur].as<uint64_t>();
+    va.mu_cur = s->mu[s->cur].as<double>();
     va.U_out = s->tmp.as<float>();
     va.g_out = s->tmp.as<float>() + VN;
     va.g_transposed = 0;
@@ -1009,6 +1364,7 @@ int32_t tsat_extract_partial(tsat_solver* s, int32_t max_cands, int32_t k, int32
 {
     g_err.clear();
     RET(need_batch(s));
+    RET(need_single(s));
     if (max_cands < 1 || max_cands > s->N) return fail(TSAT_E_ARG, "max_cands must be in [1, %d]", s->N);
     if (k <= 0) k = s->params.k_partial;
     if (k <= 0) k = (int32_t)std::max<int64_t>(20, ((int64_t)s->st.V + 9999) / 10000);
@@ -1028,6 +1384,7 @@ int32_t tsat_extract_partial(tsat_solver* s, int32_t max_cands, int32_t k, int32
     va.tbl = s->table_scr.as<float>();
     va.theta = s->theta.as<float>();
     va.lits_cur = s->lits[s->cur].as<uint64_t>();
+    va.mu_cur = s->mu[s->cur].as<double>();
     va.g_out = gT.as<float>();
     va.g_transposed = 1;
     HIPCHK(launch_var(va, VOP_GRAD, var_blocks(s, s->st.V), s->stream));
@@ -1065,14 +1422,16 @@ int32_t tsat_pack_dev(tsat_solver* s, const float* assign, int32_t N, uint64_t* 
     if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
     if (N < 1 || !assign || !bits) return fail(TSAT_E_ARG, "invalid arguments");
     RET(set_dev(s));
-    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    hipStream_t st = (hipStream_t)stream; // NULL: the null (default) stream
     HIPCHK(launch_pack(assign, s->st.V, N, (N + 63) / 64, bits, 0, st));
     return TSAT_OK;
 }
 
 static int32_t dev_prepare(tsat_solver* s, const uint64_t* bits, int32_t N, hipStream_t st)
 {
+    RET(need_single(s));
     RET(ensure_scratch(s, N));
+    RET(prepare_units(s, N));
     HIPCHK(launch_expand(bits, s->st.V, (N + 63) / 64, N, s->lits_scr.as<uint64_t>(), st));
     return TSAT_OK;
 }
@@ -1084,7 +1443,7 @@ int32_t tsat_fwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
     if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
     if (N < 1 || !bits || !(tau >= 0.f)) return fail(TSAT_E_ARG, "invalid arguments");
     RET(set_dev(s));
-    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    hipStream_t st = (hipStream_t)stream; // NULL: the null (default) stream
     RET(dev_prepare(s, bits, N, st));
     tsat_params p = s->params;
     p.tau = tau;
@@ -1098,7 +1457,7 @@ int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
     if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
     if (N < 1 || N > TSAT_MAX_STEP_N || !bits || !dS || !U || !(tau >= 0.f)) return fail(TSAT_E_ARG, "invalid arguments");
     RET(set_dev(s));
-    hipStream_t st = stream ? (hipStream_t)stream : s->stream;
+    hipStream_t st = (hipStream_t)stream; // NULL: the null (default) stream
     const int32_t W = (N + 63) / 64, Np = 64 * W;
     if ((size_t)K1_of(s) * Np * 4 > 64 * 1024) return fail(TSAT_E_ARG, "table exceeds 64 KiB");
     RET(check_row_offsets(s, W));

@@ -54,13 +54,36 @@ __device__ __forceinline__ T sload(const T* p)
     return *(const __attribute__((address_space(4))) T*)p;
 }
 
-// Butterfly sum over the 64 lanes.  Lanes l and l^m add the same two values
-// (commutative), so every lane ends with the bitwise-identical total.
+// FP64 sum over the 64 lanes without LDS: DPP swaps inside quads, DPP
+// rotations inside rows of 16, then the four row sums read from fixed lanes.
+// Every call adds in the same order, so the result is deterministic and
+// wave-uniform (it lives in SGPRs).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-    return x;
+    x += dpp_f64<0xB1>(x);  // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E>(x);  // quad_perm [2,3,0,1]
+    x += dpp_f64<0x124>(x); // row_ror:4
+    x += dpp_f64<0x128>(x); // row_ror:8
+    const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+    const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+    return (r0 + r1) + (r2 + r3);
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
@@ -81,6 +104,9 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
 {
     extern __shared__ uint32_t lh[]; // [DT*32][KW+1]
     if (a.ctrl && a.ctrl->stop) return;
+    const FwdUnit u = a.units[blockIdx.x];
+    if (a.ictrl && a.ictrl[u.inst].frozen) return;
+    uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
     const int tid = threadIdx.x;
     const int DT = a.DT;
     const int dl = tid % DT, slot = tid / DT, S = blockDim.x / DT;
@@ -88,17 +114,17 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
     const int nb = DT * 32 * (KW + 1);
     for (int q = tid; q < nb; q += blockDim.x) lh[q] = 0;
     __syncthreads();
-    if (d < a.W2 && slot < S) {
+    if (d < a.Dn && slot < S) {
         uint32_t pl[KW][B];
 #pragma unroll
         for (int r = 0; r < KW; ++r)
 #pragma unroll
             for (int b = 0; b < B; ++b) pl[r][b] = 0;
         uint32_t n = 0;
-        const int64_t c0 = (int64_t)blockIdx.x * S * a.CPT + slot;
+        const int64_t c0 = u.c0 + slot;
         for (int it = 0; it < a.CPT; ++it) {
             const int64_t c = c0 + (int64_t)it * S;
-            if (c >= a.Cb) break;
+            if (c >= u.c1) break;
             uint32_t ge[KW];
 #pragma unroll
             for (int r = 0; r < KW; ++r) ge[r] = 0;
@@ -147,7 +173,7 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
         if (!val) continue;
         const int cl = q / (KW + 1), r = q % (KW + 1);
         const int dd = blockIdx.y * DT + cl / 32;
-        if (dd < a.W2) atomicAdd(&a.H[(size_t)(blockIdx.y * DT * 32 + cl) * a.K1 + r], val);
+        if (dd < a.Dn) atomicAdd(&H[(size_t)(blockIdx.y * DT * 32 + cl) * a.K1 + r], val);
     }
 }
 
@@ -157,6 +183,9 @@ __global__ __launch_bounds__(256) void fwd_hist_wide_kernel(FwdArgs a)
 {
     extern __shared__ uint32_t lh[]; // [DT*32][K1]
     if (a.ctrl && a.ctrl->stop) return;
+    const FwdUnit u = a.units[blockIdx.x];
+    if (a.ictrl && a.ictrl[u.inst].frozen) return;
+    uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
     const int tid = threadIdx.x;
     const int DT = a.DT;
     const int dl = tid % DT, slot = tid / DT, S = blockDim.x / DT;
@@ -165,11 +194,11 @@ __global__ __launch_bounds__(256) void fwd_hist_wide_kernel(FwdArgs a)
     const int nb = DT * 32 * K1;
     for (int q = tid; q < nb; q += blockDim.x) lh[q] = 0;
     __syncthreads();
-    if (d < a.W2 && slot < S) {
-        const int64_t c0 = (int64_t)blockIdx.x * S * a.CPT + slot;
+    if (d < a.Dn && slot < S) {
+        const int64_t c0 = u.c0 + slot;
         for (int it = 0; it < a.CPT; ++it) {
             const int64_t c = c0 + (int64_t)it * S;
-            if (c >= a.Cb) break;
+            if (c >= u.c1) break;
             uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
             for (int q = 0; q < a.KW; ++q) {
                 const uint32_t code = a.codes[c * a.KW + q];
@@ -195,7 +224,7 @@ __global__ __launch_bounds__(256) void fwd_hist_wide_kernel(FwdArgs a)
         if (!val) continue;
         const int cl = q / K1;
         const int dd = blockIdx.y * DT + cl / 32;
-        if (dd < a.W2) atomicAdd(&a.H[(size_t)(blockIdx.y * DT * 32 + cl) * K1 + (q % K1)], val);
+        if (dd < a.Dn) atomicAdd(&H[(size_t)(blockIdx.y * DT * 32 + cl) * K1 + (q % K1)], val);
     }
 }
 
@@ -215,53 +244,76 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
     Ctrl* ctrl = a.ctrl;
     if (ctrl && ctrl->stop) return;
     const int tid = threadIdx.x;
+    const int b = blockIdx.x; // instance
     const int K1 = a.K1;
+    const int64_t t = ctrl ? ctrl->t : 0;
+    if (b == 0 && tid == 0 && ctrl && a.update) {
+        // schedule scalars of the pending update:
+        // lr(t) = max(lr_min, lr0 decay^floor((t mod restart)/every))
+        const int64_t phase = a.restart > 0 ? t % a.restart : t;
+        const int64_t e = a.every > 0 ? phase / a.every : 0;
+        double lr = a.lr0 * pow(a.decay, (double)e);
+        if (lr < a.lr_min) lr = a.lr_min;
+        const double tt = (double)(t + 1);
+        const double bc1 = 1.0 - pow(a.beta1, tt);
+        const double bc2 = 1.0 - pow(a.beta2, tt);
+        ctrl->lr = lr;
+        ctrl->f_decay = (float)(1.0 - lr * a.weight_decay);
+        ctrl->f_step = (float)(lr / bc1);
+        ctrl->f_isbc2 = (float)(1.0 / sqrt(bc2));
+    }
+    InstCtrl* ic = a.ictrl ? a.ictrl + b : nullptr;
+    if (ic && ic->frozen) return; // nothing accumulated for a frozen instance
+    const InstInfo info = a.info[b];
+    uint32_t* Hb = a.H + (size_t)b * a.Np * K1;
+    float* tb = a.table ? a.table + (size_t)b * K1 * a.Np : nullptr;
+    const size_t ob = (size_t)b * a.N;
     double loss = 0.0;
     int64_t best = -1;
     int32_t bidx = 0x7fffffff, satc = 0x7fffffff;
     for (int i = tid; i < a.Np; i += blockDim.x) {
-        uint32_t* h = a.H + (size_t)i * K1;
+        uint32_t* h = Hb + (size_t)i * K1;
         if (i >= a.N) {
             for (int r = 0; r < K1; ++r) {
-                if (a.table) a.table[(size_t)r * a.Np + i] = 0.0f;
+                if (tb) tb[(size_t)r * a.Np + i] = 0.0f;
                 h[r] = 0;
             }
             continue;
         }
         int r0 = -1;
         for (int r = 0; r < K1; ++r) {
-            const uint64_t hr = (uint64_t)h[r] + (r == 0 ? (uint64_t)a.n_empty : 0);
+            const uint64_t hr = (uint64_t)h[r] + (r == 0 ? (uint64_t)info.n_empty : 0);
             if (hr > 0) { r0 = r; break; }
         }
         double D = 0.0, num = 0.0;
         if (r0 >= 0) {
             for (int r = 0; r < K1; ++r) {
-                const double hr = (double)h[r] + (r == 0 ? (double)a.n_empty : 0.0);
+                const double hr = (double)h[r] + (r == 0 ? (double)info.n_empty : 0.0);
                 const double w = exp(-a.tau * (double)(r - r0));
                 D += hr * w;
                 num += (double)r * hr * w;
             }
         }
         const double S = (r0 >= 0) ? num / D : 0.0;
-        const int64_t unsat = (int64_t)h[0] + a.n_empty;
-        const int64_t sat = a.C - unsat;
-        if (a.S_out) a.S_out[i] = (float)S;
-        if (a.S64_out) a.S64_out[i] = S;
-        if (a.sat_out) a.sat_out[i] = sat;
+        const int64_t unsat = (int64_t)h[0] + info.n_empty;
+        const int64_t sat = info.C - unsat;
+        if (a.S_out) a.S_out[ob + i] = (float)S;
+        if (a.S64_out) a.S64_out[ob + i] = S;
+        if (a.sat_out) a.sat_out[ob + i] = sat;
         loss += S;
         if (sat > best) { best = sat; bidx = i; }
         if (unsat == 0 && i < satc) satc = i;
-        const double up = a.dS ? (double)a.dS[i] : -1.0;
+        const double up = a.dS ? (double)a.dS[ob + i] : -1.0;
         for (int r = 0; r < K1; ++r) {
-            if (a.table) {
-                double t = 0.0;
+            if (tb) {
+                double tv = 0.0;
                 if (r0 >= 0) {
                     const double w = exp(-a.tau * (double)(r - r0));
-                    t = up * (w / D) * (1.0 - a.tau * ((double)r - S));
+                    tv = up * (w / D) * (1.0 - a.tau * ((double)r - S));
                 }
-                a.table[(size_t)r * a.Np + i] = (float)t;
+                tb[(size_t)r * a.Np + i] = (float)tv;
             }
-            if (a.H_last) a.H_last[(size_t)i * K1 + r] = h[r] + (r == 0 ? (uint32_t)a.n_empty : 0u);
+            if (a.H_last) a.H_last[(ob + i) * K1 + r] = h[r] + (r == 0 ? (uint32_t)info.n_empty : 0u);
             if (a.zero_H) h[r] = 0;
         }
     }
@@ -270,50 +322,38 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
     s_bidx[tid] = bidx;
     s_sat[tid] = satc;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            s_loss[tid] += s_loss[tid + s];
-            if (s_best[tid + s] > s_best[tid] || (s_best[tid + s] == s_best[tid] && s_bidx[tid + s] < s_bidx[tid])) {
-                s_best[tid] = s_best[tid + s];
-                s_bidx[tid] = s_bidx[tid + s];
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st) {
+            s_loss[tid] += s_loss[tid + st];
+            if (s_best[tid + st] > s_best[tid] || (s_best[tid + st] == s_best[tid] && s_bidx[tid + st] < s_bidx[tid])) {
+                s_best[tid] = s_best[tid + st];
+                s_bidx[tid] = s_bidx[tid + st];
             }
-            if (s_sat[tid + s] < s_sat[tid]) s_sat[tid] = s_sat[tid + s];
+            if (s_sat[tid + st] < s_sat[tid]) s_sat[tid] = s_sat[tid + st];
         }
         __syncthreads();
     }
-    if (tid == 0 && ctrl) {
-        const int64_t t = ctrl->t;
-        ctrl->loss = -s_loss[0];
-        ctrl->best_cand = s_bidx[0];
-        ctrl->best_sat = s_best[0];
-        ctrl->witness_pending = 0;
+    if (tid == 0 && ic) {
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        if (ic->start_time == 0) ic->start_time = now;
+        ic->loss = -s_loss[0];
+        ic->best_cand = s_bidx[0];
+        ic->best_sat = s_best[0];
+        ic->witness_pending = 0;
         const bool any_sat = s_sat[0] != 0x7fffffff;
-        if (any_sat && ctrl->first_sat_step < 0) {
-            ctrl->first_sat_step = t;
-            ctrl->sat_cand = s_sat[0];
-            ctrl->witness_pending = 1;
+        if (any_sat && ic->first_sat_step < 0) {
+            ic->first_sat_step = t;
+            ic->sat_cand = s_sat[0];
+            ic->sat_time = now;
+            ic->witness_pending = 1;
         }
-        if ((double)s_best[0] > a.conv_frac * (double)a.C && ctrl->first_conv_step < 0) ctrl->first_conv_step = t;
-        if (a.update) {
-            if (any_sat && ctrl->stop_on_sat) {
-                ctrl->stop = 1;
-                ctrl->witness_pending = 0;
-            } else {
-                // lr(t) = max(lr_min, lr0 decay^floor((t mod restart)/every))
-                const int64_t phase = a.restart > 0 ? t % a.restart : t;
-                const int64_t e = a.every > 0 ? phase / a.every : 0;
-                double lr = a.lr0 * pow(a.decay, (double)e);
-                if (lr < a.lr_min) lr = a.lr_min;
-                const double tt = (double)(t + 1);
-                const double bc1 = 1.0 - pow(a.beta1, tt);
-                const double bc2 = 1.0 - pow(a.beta2, tt);
-                ctrl->lr = lr;
-                ctrl->f_decay = (float)(1.0 - lr * a.weight_decay);
-                ctrl->f_step = (float)(lr / bc1);
-                ctrl->f_isbc2 = (float)(1.0 / sqrt(bc2));
-                ctrl->t = t + 1;
-                ctrl->updates += 1;
-            }
+        if ((double)s_best[0] > a.conv_frac * (double)info.C && ic->first_conv_step < 0) ic->first_conv_step = t;
+        if (a.update && ctrl && any_sat && ctrl->stop_on_sat) {
+            // freeze: the current bits keep the witness, no more updates
+            ic->frozen = 1;
+            ic->witness_pending = 0;
+            const int nf = atomicAdd(&ctrl->n_frozen, 1) + 1;
+            if (nf >= a.n_inst) ctrl->stop = 1;
         }
     }
 }
@@ -331,18 +371,244 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
 
 enum { OP_STEP = 0, OP_GRAD = 1, OP_ADJ = 2, OP_BINARIZE = 3 };
 
-template <int J, int OP>
-__global__ __launch_bounds__(256) void var_kernel(VarArgs a)
+struct StepScalars {
+    float f_decay, f_step, f_isbc2;
+    float b1, b2, omb1, omb2, eps;
+};
+
+__device__ __forceinline__ StepScalars load_scalars(const VarArgs& a, int op)
 {
-    extern __shared__ float s_tbl[]; // [K1][Np]
-    if (OP == OP_STEP && a.ctrl->stop) {
-        // no update after a stop: keep the next buffer equal to the current one
-        const size_t n = (size_t)2 * a.V * a.W;
-        for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-            a.lits_next[e] = a.lits_cur[e];
+    StepScalars c;
+    c.f_decay = 1.f;
+    c.f_step = 0.f;
+    c.f_isbc2 = 1.f;
+    if (op == OP_STEP) {
+        c.f_decay = a.ctrl->f_decay;
+        c.f_step = a.ctrl->f_step;
+        c.f_isbc2 = a.ctrl->f_isbc2;
+    }
+    c.b1 = a.beta1;
+    c.b2 = a.beta2;
+    c.omb1 = a.one_minus_beta1;
+    c.omb2 = a.one_minus_beta2;
+    c.eps = a.eps;
+    return c;
+}
+
+// Eq. 5 clamp of a row mean: |mu| < 1e-12 becomes +-1e-12 (0 -> +1e-12).
+__device__ __forceinline__ double clamp_mu(double mu, bool& clamped)
+{
+    clamped = fabs(mu) < 1e-12;
+    return clamped ? ((mu >= 0.0) ? 1e-12 : -1e-12) : mu;
+}
+
+// Pack B(theta_norm) of one variable row into its two literal rows.
+template <int J>
+__device__ __forceinline__ void write_bits(const VarArgs& a, uint32_t v, uint32_t lane, const float (&th)[J],
+                                          const bool (&valid)[J], bool pos)
+{
+    const int W = a.W;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (j >= W) break;
+        const bool p = valid[j] && (pos ? th[j] > 0.f : th[j] < 0.f);
+        const uint64_t bal = ballot64(p);
+        const uint64_t vm = ballot64(valid[j]);
+        if (lane == 0) {
+            a.lits_next[(size_t)(2 * v) * W + j] = bal;
+            a.lits_next[(size_t)(2 * v + 1) * W + j] = ~bal & vm;
+        }
+    }
+}
+
+// Row loads of theta (and the optimizer moments for the step).
+template <int J, int OP, bool FULL = false>
+__device__ __forceinline__ void load_row(const VarArgs& a, uint32_t v, uint32_t lane, float (&th)[J], float (&mm)[J],
+                                         float (&vv)[J], bool (&valid)[J])
+{
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int i = 64 * j + (int)lane;
+        valid[j] = FULL || i < a.N; // FULL: N == 64 J, every lane holds a candidate
+        const size_t idx = (size_t)v * a.N + i;
+        th[j] = (OP != OP_ADJ && valid[j]) ? a.theta[idx] : 0.f;
+        mm[j] = (OP == OP_STEP && valid[j]) ? a.m[idx] : 0.f;
+        vv[j] = (OP == OP_STEP && valid[j]) ? a.v[idx] : 0.f;
+    }
+}
+
+// Everything after U: stores of U (adjoint op), Eq. 5 backward, stores of g
+// (gradient op), AdamW, witness, new row mean, re-binarization (step op).
+template <int J, int OP>
+__device__ __forceinline__ void var_tail(const VarArgs& a, const StepScalars& c, uint32_t v, uint32_t lane,
+                                         float (&th)[J], const float (&mm0)[J], const float (&vv0)[J],
+                                         const bool (&valid)[J], double mu, bool clamped, const double (&U)[J],
+                                         const uint64_t (&oP)[J], int witness, int wcand, int& bad)
+{
+    const int N = a.N;
+    if (OP == OP_ADJ || OP == OP_GRAD) {
+        if (a.U_out) {
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if (valid[j]) a.U_out[(size_t)v * N + 64 * j + lane] = (float)U[j];
+        }
+        if (OP == OP_ADJ) return;
+    }
+    // Eq. 5 backward: g = U / mu - (sum_i U_i theta_i) / (N mu^2)
+    float g[J];
+    if (a.mode == 1) {
+        double ut = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) ut += U[j] * (double)th[j];
+        ut = wave_sum(ut);
+        const double inv_mu = 1.0 / mu;
+        const double corr = clamped ? 0.0 : ut * inv_mu * inv_mu / (double)N;
+#pragma unroll
+        for (int j = 0; j < J; ++j) g[j] = (float)(U[j] * inv_mu - corr);
+    } else {
+#pragma unroll
+        for (int j = 0; j < J; ++j) g[j] = (float)U[j];
+    }
+    if (OP == OP_GRAD) {
+        if (a.g_out) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                if (!valid[j]) continue;
+                const int i = 64 * j + lane;
+                if (a.g_transposed) a.g_out[(size_t)i * a.V + v] = g[j];
+                else a.g_out[(size_t)v * N + i] = g[j];
+            }
+        }
         return;
     }
-    if (OP != OP_BINARIZE) {
+    // AdamW (decoupled weight decay), FP32 with FP64-derived scalars
+    double s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const size_t idx = (size_t)v * N + 64 * j + lane;
+        float t = th[j] * c.f_decay;
+        const float mm = c.b1 * mm0[j] + c.omb1 * g[j];
+        const float vv = c.b2 * vv0[j] + c.omb2 * (g[j] * g[j]);
+        // hardware square root and reciprocal (1 ulp each)
+        const float denom = __builtin_amdgcn_sqrtf(vv) * c.f_isbc2 + c.eps;
+        t = t - c.f_step * (mm * __builtin_amdgcn_rcpf(denom));
+        th[j] = valid[j] ? t : 0.f;
+        if (valid[j]) {
+            if (!(__builtin_isfinite(t) && __builtin_isfinite(mm) && __builtin_isfinite(vv))) bad = 1;
+            a.theta[idx] = t;
+            a.m[idx] = mm;
+            a.v[idx] = vv;
+        }
+        s2 += (double)th[j];
+    }
+    if (witness && lane == 0) a.witness[v] = (uint8_t)((oP[wcand >> 6] >> (wcand & 63)) & 1u);
+    bool pos = true;
+    if (a.mode == 1) {
+        const double mu2 = wave_sum(s2) / (double)N;
+        if (lane == 0) a.mu_next[v] = mu2;
+        pos = mu2 >= 0.0; // the clamp maps a zero mean to +1e-12
+    }
+    write_bits<J>(a, v, lane, th, valid, pos);
+}
+
+// After a stop (stop_on_sat), the step kernel keeps the next bit buffer and
+// row means equal to the current ones so the host's buffer swap stays valid.
+__device__ __forceinline__ void copy_bits_on_stop(const VarArgs& a)
+{
+    const size_t n = (size_t)2 * a.V * a.W;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) a.lits_next[e] = a.lits_cur[e];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)a.V; e += stride)
+        a.mu_next[e] = a.mu_cur[e];
+}
+
+// A variable of an instance frozen on a satisfying candidate keeps its bits
+// and row mean (the next buffers get the current ones) and is not updated.
+template <int J>
+__device__ __forceinline__ void keep_variable(const VarArgs& a, uint32_t v, uint32_t lane)
+{
+    const int W = a.W;
+    if (lane < (uint32_t)(2 * W)) {
+        const size_t e = (size_t)(2 * v) * W + lane;
+        a.lits_next[e] = a.lits_cur[e];
+    }
+    if (lane == 0) a.mu_next[v] = a.mu_cur[v];
+}
+
+struct VarInst {
+    uint32_t inst;
+    bool frozen;
+    int witness, wcand;
+};
+
+template <int OP>
+__device__ __forceinline__ VarInst var_instance(const VarArgs& a, uint32_t v)
+{
+    VarInst r;
+    r.inst = a.var_inst ? sload(a.var_inst + v) : 0u;
+    r.frozen = false;
+    r.witness = 0;
+    r.wcand = 0;
+    if (OP == OP_STEP && a.ictrl) {
+        const InstCtrl* ic = a.ictrl + r.inst;
+        r.frozen = sload(&ic->frozen) != 0;
+        r.witness = sload(&ic->witness_pending);
+        r.wcand = sload(&ic->sat_cand);
+    }
+    return r;
+}
+
+// The update kernel advances the iteration index once all of it has run
+// (the next kernel on the stream sees it).
+__device__ __forceinline__ void advance_step(const VarArgs& a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctrl->t += 1;
+        a.ctrl->updates += 1;
+    }
+}
+
+// theta -> row means and literal rows (initialization, set_logits/state).
+template <int J>
+__global__ __launch_bounds__(256) void binarize_kernel(VarArgs a)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        float th[J];
+        bool valid[J];
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = 64 * j + (int)lane;
+            valid[j] = i < a.N;
+            th[j] = valid[j] ? a.theta[(size_t)v * a.N + i] : 0.f;
+            s += (double)th[j];
+        }
+        bool pos = true;
+        if (a.mode == 1) {
+            const double mu = wave_sum(s) / (double)a.N;
+            if (lane == 0) a.mu_next[v] = mu;
+            pos = mu >= 0.0;
+        } else if (lane == 0) {
+            a.mu_next[v] = 1.0;
+        }
+        write_bits<J>(a, v, lane, th, valid, pos);
+    }
+}
+
+// Generic widths: records (k-1, the other k-1 literal indices), the dL/dR
+// table in LDS indexed by R, FP64 accumulation.
+template <int J, int OP, bool MULTI>
+__global__ __launch_bounds__(256) void var_kernel(VarArgs a)
+{
+    extern __shared__ float s_tbl[]; // [K1][Np] (one instance)
+    if (OP == OP_STEP && a.ctrl->stop) {
+        copy_bits_on_stop(a);
+        return;
+    }
+    if (!MULTI) {
         const int nt = a.K1 * a.Np;
         for (int q = threadIdx.x; q < nt; q += blockDim.x) s_tbl[q] = a.tbl[q];
         __syncthreads();
@@ -352,67 +618,31 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
     // the variable index in SGPRs and issues scalar loads)
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
     const uint32_t nwaves = uniform(gridDim.x * 4u);
-    const int N = a.N, W = a.W, Np = a.Np;
-
-    float f_decay = 1.f, f_step = 0.f, f_isbc2 = 1.f;
-    int witness = 0, wcand = 0;
-    if (OP == OP_STEP) {
-        f_decay = a.ctrl->f_decay;
-        f_step = a.ctrl->f_step;
-        f_isbc2 = a.ctrl->f_isbc2;
-        witness = a.ctrl->witness_pending;
-        wcand = a.ctrl->sat_cand;
-    }
-    const float b1 = a.beta1, b2 = a.beta2, omb1 = a.one_minus_beta1, omb2 = a.one_minus_beta2, eps = a.eps;
+    const int W = a.W, Np = a.Np;
+    const StepScalars c = load_scalars(a, OP);
     const char* lit_base = (const char*)a.lits_cur;
     const uint32_t row_bytes = (uint32_t)W * 8u;
     int bad = 0;
 
     for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
-        float th[J];
-        bool valid[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int i = 64 * j + (int)lane;
-            valid[j] = i < N;
-            th[j] = (OP != OP_ADJ && valid[j]) ? a.theta[(size_t)v * N + i] : 0.f;
-        }
-        double mu = 1.0;
-        bool clamped = false;
-        if (a.mode == 1 && OP != OP_ADJ) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < J; ++j) s += (double)th[j];
-            s = wave_sum(s);
-            mu = s / (double)N;
-            if (fabs(mu) < 1e-12) {
-                clamped = true;
-                mu = (mu >= 0.0) ? 1e-12 : -1e-12;
-            }
-        }
-        if (OP == OP_BINARIZE) {
-            const bool pos = mu > 0.0;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                if (j >= W) break;
-                const bool p = valid[j] && (pos ? th[j] > 0.f : th[j] < 0.f);
-                const uint64_t bal = ballot64(p);
-                const uint64_t vm = ballot64(valid[j]);
-                if (lane == 0) {
-                    a.lits_next[(size_t)(2 * v) * W + j] = bal;
-                    a.lits_next[(size_t)(2 * v + 1) * W + j] = ~bal & vm;
-                }
-            }
+        const VarInst vi = var_instance<OP>(a, v);
+        if (vi.frozen) {
+            keep_variable<J>(a, v, lane);
             continue;
         }
-        // own literal rows
+        const float* tg = a.tbl + (size_t)vi.inst * a.K1 * Np; // this instance's table (MULTI)
+        float th[J], mm[J], vv[J];
+        bool valid[J];
+        load_row<J, OP>(a, v, lane, th, mm, vv, valid);
+        bool clamped = false;
+        const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+        // own literal rows (buffers carry 16 words of padding: J-word reads stay in bounds)
         const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
         uint64_t oP[J], oN[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            // J is an upper bound on the row length W: words past W are 0
-            oP[j] = j < W ? sload(ownp + j) : 0ull;
-            oN[j] = j < W ? sload(ownp + W + j) : 0ull;
+            oP[j] = sload(ownp + j);
+            oN[j] = sload(ownp + W + j);
         }
         // FP64 accumulation: the error stays at the table's FP32 rounding
         // whatever the variable's degree
@@ -431,93 +661,168 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
                 const uint32_t off = sload(a.occ_data + q + 1 + e) * row_bytes;
                 const uint64_t* row = (const uint64_t*)(lit_base + off);
 #pragma unroll
-                for (int j = 0; j < J; ++j)
-                    if (j < W) R[j] = add_lane_bit(R[j], sload(row + j));
+                for (int j = 0; j < J; ++j) R[j] = add_lane_bit(R[j], sload(row + j));
             }
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 if (j >= W) break;
-                const double val = (double)s_tbl[R[j] * Np + 64 * j + lane];
+                const int ti = R[j] * Np + 64 * j + lane;
+                const double val = (double)(MULTI ? tg[ti] : s_tbl[ti]);
                 U[j] = neg ? U[j] - val : U[j] + val;
             }
             q += 1 + k1;
         }
-        if (OP == OP_ADJ || OP == OP_GRAD) {
-            if (a.U_out) {
-#pragma unroll
-                for (int j = 0; j < J; ++j)
-                    if (valid[j]) a.U_out[(size_t)v * N + 64 * j + lane] = (float)U[j];
-            }
-            if (OP == OP_ADJ) continue;
-        }
-        // Eq. 5 backward: g = U / mu - (sum_i U_i theta_i) / (N mu^2)
-        float g[J];
-        if (a.mode == 1) {
-            double ut = 0.0;
-#pragma unroll
-            for (int j = 0; j < J; ++j) ut += U[j] * (double)th[j];
-            ut = wave_sum(ut);
-            const double corr = clamped ? 0.0 : ut / ((double)N * mu * mu);
-#pragma unroll
-            for (int j = 0; j < J; ++j) g[j] = (float)(U[j] / mu - corr);
-        } else {
-#pragma unroll
-            for (int j = 0; j < J; ++j) g[j] = (float)U[j];
-        }
-        if (OP == OP_GRAD) {
-            if (a.g_out) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    if (!valid[j]) continue;
-                    const int i = 64 * j + lane;
-                    if (a.g_transposed) a.g_out[(size_t)i * a.V + v] = g[j];
-                    else a.g_out[(size_t)v * N + i] = g[j];
-                }
-            }
-            continue;
-        }
-        // AdamW (decoupled weight decay), FP32 with FP64-derived scalars
-        float mm[J], vv[J];
-        double s2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const size_t idx = (size_t)v * N + 64 * j + lane;
-            mm[j] = valid[j] ? a.m[idx] : 0.f;
-            vv[j] = valid[j] ? a.v[idx] : 0.f;
-            float t = th[j] * f_decay;
-            mm[j] = b1 * mm[j] + omb1 * g[j];
-            vv[j] = b2 * vv[j] + omb2 * (g[j] * g[j]);
-            const float denom = sqrtf(vv[j]) * f_isbc2 + eps;
-            t = t - f_step * (mm[j] / denom);
-            th[j] = valid[j] ? t : 0.f;
-            if (valid[j] && !(__builtin_isfinite(t) && __builtin_isfinite(mm[j]) && __builtin_isfinite(vv[j]))) bad = 1;
-            if (valid[j]) {
-                a.theta[idx] = th[j];
-                a.m[idx] = mm[j];
-                a.v[idx] = vv[j];
-            }
-            s2 += (double)th[j];
-        }
-        if (witness && lane == 0) a.witness[v] = (uint8_t)((oP[wcand >> 6] >> (wcand & 63)) & 1u);
-        bool pos = true;
-        if (a.mode == 1) {
-            s2 = wave_sum(s2);
-            pos = (s2 / (double)N) >= 0.0; // the clamp maps a zero mean to +1e-12
-        }
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (j >= W) break;
-            const bool p = valid[j] && (pos ? th[j] > 0.f : th[j] < 0.f);
-            const uint64_t bal = ballot64(p);
-            const uint64_t vm = ballot64(valid[j]);
-            if (lane == 0) {
-                a.lits_next[(size_t)(2 * v) * W + j] = bal;
-                a.lits_next[(size_t)(2 * v + 1) * W + j] = ~bal & vm;
-            }
-        }
+        var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
     }
     if (OP == OP_STEP) {
         if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
+        advance_step(a);
+    }
+}
+
+// Every clause has the same width k = KO + 1 (KO other literals per record,
+// no header).  Occurrences are taken G records at a time: all their literal
+// rows are requested through the scalar cache before the first wait (the
+// buffers are padded, so the loads need no guards; records past the end of
+// the variable are masked out).  Per candidate and sign, integer counters
+// c_o = #{occurrences whose other literals hold >= o true ones}
+// (o = 1..KO) are accumulated from bit-sliced cumulative masks; then
+// n_O = c_O - c_{O+1} (c_0 = degree) and
+// U = sum_O n+_O g[x + O] - sum_O n-_O g[1 - x + O], x the candidate's own
+// value.  The dL/dR table of the lane's candidates sits in registers.
+template <int KO>
+__device__ __forceinline__ void cum_masks(const uint64_t (&w)[KO], uint64_t (&ge)[KO])
+{
+#pragma unroll
+    for (int o = 0; o < KO; ++o) ge[o] = 0;
+#pragma unroll
+    for (int e = 0; e < KO; ++e) {
+#pragma unroll
+        for (int o = KO - 1; o >= 1; --o) ge[o] |= ge[o - 1] & w[e];
+        ge[0] |= w[e];
+    }
+}
+
+template <int J, int KO, int G, int OP, bool FULL>
+__global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) {
+        copy_bits_on_stop(a);
+        return;
+    }
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const int W = a.W, Np = a.Np;
+    const StepScalars c = load_scalars(a, OP);
+    const char* lit_base = (const char*)a.lits_cur;
+    const uint32_t row_bytes = (uint32_t)W * 8u;
+    constexpr int K1 = KO + 2; // R in 0..KO+1
+    float gt[K1][J];
+    uint32_t gt_inst = 0xffffffffu;
+    int bad = 0;
+
+    for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        const VarInst vi = var_instance<OP>(a, v);
+        if (vi.frozen) {
+            keep_variable<J>(a, v, lane);
+            continue;
+        }
+        if (vi.inst != gt_inst) {
+            // the dL/dR table of this instance for the lane's candidates
+            gt_inst = vi.inst;
+            const float* tg = a.tbl + (size_t)vi.inst * K1 * Np;
+#pragma unroll
+            for (int r = 0; r < K1; ++r)
+#pragma unroll
+                for (int j = 0; j < J; ++j) gt[r][j] = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
+        }
+        float th[J], mm[J], vv[J];
+        bool valid[J];
+        load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
+        bool clamped = false;
+        const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+        const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+        uint64_t oP[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+        uint32_t cnt[2][KO][J];
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+            for (int o = 0; o < KO; ++o)
+#pragma unroll
+                for (int j = 0; j < J; ++j) cnt[sg][o][j] = 0;
+        const uint32_t r0 = sload(a.occ_off + v), rm = sload(a.occ_mid + v), r1 = sload(a.occ_off + v + 1);
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const uint32_t beg = sg ? rm : r0, end = sg ? r1 : rm;
+            // the codes of the next group are requested with the rows of the
+            // current one: one scalar-memory round trip per group
+            uint32_t code_next[G][KO];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int e = 0; e < KO; ++e) code_next[g][e] = sload(a.occ_data + (size_t)(beg + g) * KO + e);
+            for (uint32_t q = beg; q < end; q += G) {
+                uint32_t code[G][KO];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int e = 0; e < KO; ++e) code[g][e] = code_next[g][e];
+                uint64_t w[G][KO][J];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int e = 0; e < KO; ++e) {
+                        const uint64_t* row = (const uint64_t*)(lit_base + code[g][e] * row_bytes);
+#pragma unroll
+                        for (int j = 0; j < J; ++j) w[g][e][j] = sload(row + j);
+                    }
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int e = 0; e < KO; ++e) code_next[g][e] = sload(a.occ_data + (size_t)(q + G + g) * KO + e);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bool live = q + g < end; // wave-uniform
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        uint64_t wj[KO], ge[KO];
+#pragma unroll
+                        for (int e = 0; e < KO; ++e) wj[e] = w[g][e][j];
+                        cum_masks<KO>(wj, ge);
+#pragma unroll
+                        for (int o = 0; o < KO; ++o) cnt[sg][o][j] = add_lane_bit(cnt[sg][o][j], live ? ge[o] : 0ull);
+                    }
+                }
+            }
+        }
+        const uint32_t dp = rm - r0, dn = r1 - rm;
+        double U[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t x = add_lane_bit(0u, oP[j]); // own value of this lane's candidate
+            float u = 0.f;
+#pragma unroll
+            for (int O = 0; O <= KO; ++O) {
+                const uint32_t cp_hi = (O < KO) ? cnt[0][O][j] : 0u, cn_hi = (O < KO) ? cnt[1][O][j] : 0u;
+                const uint32_t cp_lo = (O == 0) ? dp : cnt[0][O - 1][j];
+                const uint32_t cn_lo = (O == 0) ? dn : cnt[1][O - 1][j];
+                const float np = (float)(cp_lo - cp_hi), nn = (float)(cn_lo - cn_hi);
+                // positive occurrence: R = x + O; negative: R = (1 - x) + O
+                const float gp = x ? gt[O + 1][j] : gt[O][j];
+                const float gn = x ? gt[O][j] : gt[O + 1][j];
+                u = fmaf(np, gp, u);
+                u = fmaf(-nn, gn, u);
+            }
+            U[j] = (double)u;
+        }
+        var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
+    }
+    if (OP == OP_STEP) {
+        if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
+        advance_step(a);
     }
 }
 
@@ -739,8 +1044,9 @@ static hipError_t launch_fwd_k(const FwdArgs& a, dim3 grid, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_fwd(const FwdArgs& a, dim3 grid, hipStream_t st)
+hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st)
 {
+    const dim3 grid((unsigned)nunits, (unsigned)tiles, 1);
     switch (a.KW) {
     case 1: return launch_fwd_k<1, 8>(a, grid, st);
     case 2: return launch_fwd_k<2, 8>(a, grid, st);
@@ -756,31 +1062,133 @@ hipError_t launch_fwd(const FwdArgs& a, dim3 grid, hipStream_t st)
 
 hipError_t launch_smin(const SminArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(smin_kernel, dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(smin_kernel, dim3((unsigned)a.n_inst), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int J, bool MULTI>
+static hipError_t launch_var_jm(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    const size_t lds = MULTI ? 0 : (size_t)a.K1 * a.Np * sizeof(float);
+    switch (op) {
+    case OP_STEP: hipLaunchKernelGGL((var_kernel<J, OP_STEP, MULTI>), dim3(blocks), dim3(256), lds, st, a); break;
+    case OP_GRAD: hipLaunchKernelGGL((var_kernel<J, OP_GRAD, MULTI>), dim3(blocks), dim3(256), lds, st, a); break;
+    case OP_ADJ: hipLaunchKernelGGL((var_kernel<J, OP_ADJ, MULTI>), dim3(blocks), dim3(256), lds, st, a); break;
+    default: hipLaunchKernelGGL((binarize_kernel<J>), dim3(blocks), dim3(256), 0, st, a); break;
+    }
     return hipGetLastError();
 }
 
 template <int J>
 static hipError_t launch_var_j(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
-    const size_t lds = (op == OP_BINARIZE) ? 0 : (size_t)a.K1 * a.Np * sizeof(float);
+    return a.var_inst ? launch_var_jm<J, true>(a, op, blocks, st) : launch_var_jm<J, false>(a, op, blocks, st);
+}
+
+// resident blocks per CU of the kernel a launch with these arguments would use
+template <class K>
+static int occupancy_of(K kernel, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 256, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template <int J, int KO, int G, bool FULL>
+static hipError_t launch_pure_jkgf(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
     switch (op) {
-    case OP_STEP: hipLaunchKernelGGL((var_kernel<J, OP_STEP>), dim3(blocks), dim3(256), lds, st, a); break;
-    case OP_GRAD: hipLaunchKernelGGL((var_kernel<J, OP_GRAD>), dim3(blocks), dim3(256), lds, st, a); break;
-    case OP_ADJ: hipLaunchKernelGGL((var_kernel<J, OP_ADJ>), dim3(blocks), dim3(256), lds, st, a); break;
-    default: hipLaunchKernelGGL((var_kernel<J, OP_BINARIZE>), dim3(blocks), dim3(256), lds, st, a); break;
+    case OP_STEP: hipLaunchKernelGGL((var_pure_kernel<J, KO, G, OP_STEP, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_GRAD: hipLaunchKernelGGL((var_pure_kernel<J, KO, G, OP_GRAD, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((var_pure_kernel<J, KO, G, OP_ADJ, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
 }
 
+template <int J, int KO, int G>
+static hipError_t launch_pure_jkg(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    if (a.N == 64 * J) return launch_pure_jkgf<J, KO, G, true>(a, op, blocks, st);
+    return launch_pure_jkgf<J, KO, G, false>(a, op, blocks, st);
+}
+
+// records per scalar-load group (tuning knob): up to 4 for rows of up to 4
+// words, 2 up to 8 words, else 1
+static int pure_group(const VarArgs& a, int J)
+{
+    if (J <= 4 && a.group >= 4) return 4;
+    if (J <= 8 && a.group >= 2) return 2;
+    return 1;
+}
+
+template <int J, int KO>
+static hipError_t launch_pure_jk(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    switch (pure_group(a, J)) {
+    case 4: return launch_pure_jkg<J, KO, (J <= 4 ? 4 : 1)>(a, op, blocks, st);
+    case 2: return launch_pure_jkg<J, KO, (J <= 8 ? 2 : 1)>(a, op, blocks, st);
+    default: return launch_pure_jkg<J, KO, 1>(a, op, blocks, st);
+    }
+}
+
+template <int J>
+static hipError_t launch_pure_j(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    switch (a.pure_k) {
+    case 2: return launch_pure_jk<J, 1>(a, op, blocks, st);
+    case 3: return launch_pure_jk<J, 2>(a, op, blocks, st);
+    default: return launch_pure_jk<J, 3>(a, op, blocks, st);
+    }
+}
+
 hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
+    const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;
     switch (a.W) {
-    case 1: return launch_var_j<1>(a, op, blocks, st);
-    case 2: return launch_var_j<2>(a, op, blocks, st);
-    case 3: case 4: return launch_var_j<4>(a, op, blocks, st);
-    case 5: case 6: case 7: case 8: return launch_var_j<8>(a, op, blocks, st);
-    default: return launch_var_j<16>(a, op, blocks, st);
+    case 1: return pure ? launch_pure_j<1>(a, op, blocks, st) : launch_var_j<1>(a, op, blocks, st);
+    case 2: return pure ? launch_pure_j<2>(a, op, blocks, st) : launch_var_j<2>(a, op, blocks, st);
+    case 3: case 4: return pure ? launch_pure_j<4>(a, op, blocks, st) : launch_var_j<4>(a, op, blocks, st);
+    case 5: case 6: case 7: case 8: return pure ? launch_pure_j<8>(a, op, blocks, st) : launch_var_j<8>(a, op, blocks, st);
+    default: return pure ? launch_pure_j<16>(a, op, blocks, st) : launch_var_j<16>(a, op, blocks, st);
+    }
+}
+
+template <int J, int KO>
+static int occupancy_pure(const VarArgs& a)
+{
+    switch (pure_group(a, J)) {
+    case 4: return occupancy_of(var_pure_kernel<J, KO, (J <= 4 ? 4 : 1), OP_STEP, true>, 0);
+    case 2: return occupancy_of(var_pure_kernel<J, KO, (J <= 8 ? 2 : 1), OP_STEP, true>, 0);
+    default: return occupancy_of(var_pure_kernel<J, KO, 1, OP_STEP, true>, 0);
+    }
+}
+
+template <int J>
+static int occupancy_j(const VarArgs& a, bool pure)
+{
+    if (!pure) {
+        if (a.var_inst) return occupancy_of(var_kernel<J, OP_STEP, true>, 0);
+        return occupancy_of(var_kernel<J, OP_STEP, false>, (size_t)a.K1 * a.Np * sizeof(float));
+    }
+    switch (a.pure_k) {
+    case 2: return occupancy_pure<J, 1>(a);
+    case 3: return occupancy_pure<J, 2>(a);
+    default: return occupancy_pure<J, 3>(a);
+    }
+}
+
+int var_occupancy(const VarArgs& a, int op)
+{
+    const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;
+    switch (a.W) {
+    case 1: return occupancy_j<1>(a, pure);
+    case 2: return occupancy_j<2>(a, pure);
+    case 3: case 4: return occupancy_j<4>(a, pure);
+    case 5: case 6: case 7: case 8: return occupancy_j<8>(a, pure);
+    default: return occupancy_j<16>(a, pure);
     }
 }
 

@@ -53,6 +53,14 @@ class _Report(ct.Structure):
     ]
 
 
+class _InstStatus(ct.Structure):
+    _fields_ = [
+        ("first_sat_step", _i64), ("first_converged_step", _i64), ("best_sat_count", _i64),
+        ("num_clauses", _i64), ("loss", _f64), ("start_ticks", _u64), ("sat_ticks", _u64),
+        ("best_candidate", _i32), ("sat_candidate", _i32), ("frozen", _i32), ("num_vars", _i32),
+    ]
+
+
 class _CnfInfo(ct.Structure):
     _fields_ = [
         ("num_vars", _i32), ("max_width", _i32), ("num_clauses", _i64), ("num_lits", _i64),
@@ -85,6 +93,13 @@ _SIGS = [
     ("tsat_destroy", None, [_P]),
     ("tsat_load_cnf", _i32, [_P, _i32, _i64, _P]),
     ("tsat_load_dimacs", _i32, [_P, ct.c_char_p]),
+    ("tsat_load_cnf_batch", _i32, [_P, _i32, _P, _P, _P]),
+    ("tsat_num_instances", _i32, [_P]),
+    ("tsat_num_vars", _i32, [_P]),
+    ("tsat_set_graph", _i32, [_P, _i32]),
+    ("tsat_get_instance_status", _i32, [_P, _i32, _i32, ct.POINTER(_InstStatus)]),
+    ("tsat_device_clock_hz", _i32, [_P, ct.POINTER(_f64)]),
+    ("tsat_get_witness_instance", _i32, [_P, _i32, _P, ct.POINTER(_i32)]),
     ("tsat_init_batch", _i32, [_P, _i32, _u64, _P]),
     ("tsat_step", _i32, [_P, _i32, ct.POINTER(Params), _i32, ct.POINTER(_Report)]),
     ("tsat_check", _i32, [_P, _P, _P]),
@@ -225,6 +240,41 @@ class Solver:
         self.V = V
         self.N = 0
 
+    def load_batch(self, cnfs) -> None:
+        """Load a list of ``gen.CNF`` instances as one batch."""
+        streams = [c.dimacs_stream() for c in cnfs]
+        nv = np.array([c.num_vars for c in cnfs], dtype=np.int32)
+        off = np.zeros(len(cnfs) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([s.size for s in streams])
+        lits = np.concatenate(streams).astype(np.int32) if streams else np.zeros(0, dtype=np.int32)
+        _check(lib().tsat_load_cnf_batch(self._h, len(cnfs), _ptr(nv), _ptr(off), _ptr(lits)))
+        self.V = int(lib().tsat_num_vars(self._h))
+        self.N = 0
+
+    @property
+    def num_instances(self) -> int:
+        return int(lib().tsat_num_instances(self._h))
+
+    def set_graph(self, enable: bool) -> None:
+        _check(lib().tsat_set_graph(self._h, 1 if enable else 0))
+
+    def instance_status(self, first: int = 0, count: int | None = None) -> list[dict]:
+        n = self.num_instances - first if count is None else count
+        arr = (_InstStatus * max(n, 1))()
+        _check(lib().tsat_get_instance_status(self._h, int(first), int(n), arr))
+        return [{f: getattr(arr[i], f) for f, _ in _InstStatus._fields_} for i in range(n)]
+
+    def device_clock_hz(self) -> float:
+        hz = _f64()
+        _check(lib().tsat_device_clock_hz(self._h, ct.byref(hz)))
+        return float(hz.value)
+
+    def get_witness_instance(self, inst: int, num_vars: int):
+        out = np.empty(num_vars, dtype=np.uint8)
+        c = _i32()
+        _check(lib().tsat_get_witness_instance(self._h, int(inst), _ptr(out), ct.byref(c)))
+        return out, int(c.value)
+
     @property
     def max_width(self) -> int:
         return int(lib().tsat_max_width(self._h))
@@ -249,20 +299,22 @@ class Solver:
         return Report(*[getattr(r, f) for f, _ in _Report._fields_ if f != "reserved"])
 
     def check(self):
-        sat = np.empty(self.N, dtype=np.int64)
-        ok = np.empty(self.N, dtype=np.uint8)
+        ni = self.num_instances
+        sat = np.empty((ni, self.N), dtype=np.int64)
+        ok = np.empty((ni, self.N), dtype=np.uint8)
         _check(lib().tsat_check(self._h, _ptr(sat), _ptr(ok)))
-        return sat, ok
+        return (sat[0], ok[0]) if ni == 1 else (sat, ok)
 
     def check_bits(self, packed: np.ndarray, n: int):
         p = np.ascontiguousarray(packed, dtype=np.uint64)
         W = (n + 63) // 64
         if p.shape != (self.V, W):
             raise ValueError(f"packed must have shape {(self.V, W)}")
-        sat = np.empty(n, dtype=np.int64)
-        ok = np.empty(n, dtype=np.uint8)
+        ni = self.num_instances
+        sat = np.empty((ni, n), dtype=np.int64)
+        ok = np.empty((ni, n), dtype=np.uint8)
         _check(lib().tsat_check_bits(self._h, _ptr(p), int(n), _ptr(sat), _ptr(ok)))
-        return sat, ok
+        return (sat[0], ok[0]) if ni == 1 else (sat, ok)
 
     def get_assignment(self, cand: int) -> np.ndarray:
         out = np.empty(self.V, dtype=np.uint8)
@@ -315,11 +367,14 @@ class Solver:
 
     def eval(self, params: Params | None = None):
         K1 = self.max_width + 1
-        hist = np.empty((self.N, K1), dtype=np.uint32)
-        S = np.empty(self.N, dtype=np.float64)
+        ni = self.num_instances
+        hist = np.empty((ni, self.N, K1), dtype=np.uint32)
+        S = np.empty((ni, self.N), dtype=np.float64)
         loss = _f64()
         _check(lib().tsat_eval(self._h, ct.byref(params) if params is not None else None, _ptr(hist), _ptr(S),
                                ct.byref(loss)))
+        if ni == 1:
+            return hist[0], S[0], float(loss.value)
         return hist, S, float(loss.value)
 
     def get_grad(self, params: Params | None = None):

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_defaults():
-    assert tsat.version() == 10000
+    assert tsat.version() == 10100
     p = tsat.default_params()
     assert p.tau == 1.0 and p.lr0 == 0.1 and p.lr_decay == 0.1 and p.lr_min == 1e-15
     assert (p.beta1, p.beta2, p.eps, p.weight_decay) == (0.9, 0.999, 1e-8, 1e-2)

@@ -1,0 +1,148 @@
+"""torch.autograd.Function over the HIP forward/adjoint vs the FP64 oracle and
+finite differences of the relaxed objective (Eq. 3/4 on real-valued x)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2511_07737_amd import gen, tsat
+
+from parity_util import (TOL_GRAD, abs_adjoint, grad_bound, make_state, solver_or_skip, sub_cnf)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    s = solver_or_skip()
+    if not torch.cuda.is_available():
+        pytest.skip("torch sees no GPU")
+    from paper_2511_07737_amd import autograd
+
+    yield torch, s, autograd
+    s.close()
+
+
+def mixed_cnf():
+    s = gen.structured(640, 3000, seed=4)
+    clauses = [list(s.clause(c)) for c in range(s.num_clauses)] + [[5, 5, -7], [9, -9], [13]]
+    return gen.CNF.from_clauses(645, clauses)
+
+
+def test_forward_and_backward_vs_oracle(env):
+    torch, solver, ag = env
+    cnf = mixed_cnf()
+    solver.load(cnf)
+    oc = orc.Cnf.from_gen(cnf)
+    N = 100
+    rng = np.random.default_rng(5)
+    b = rng.integers(0, 2, size=(cnf.num_vars, N)).astype(np.uint8)
+    for tau in (0.5, 1.0, 2.0):
+        print(f"[autograd] tau={tau}", flush=True)
+        A = torch.tensor(b, dtype=torch.float32, device="cuda", requires_grad=True)
+        S = ag.smoothmin_sat(A, solver, tau)
+        H = orc.histogram(oc, b)
+        w = rng.normal(size=N)
+        S_ref, table, _ = orc.smoothmin(H, tau, w)
+        assert np.allclose(S.detach().cpu().numpy(), S_ref, rtol=1e-6, atol=1e-6)
+        (S * torch.tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
+        U = A.grad.cpu().numpy()
+        U_ref = orc.adjoint(oc, b, table)
+        aU = abs_adjoint(oc, b, table)
+        # the upstream gradient is rounded to FP32 on the GPU: add its rounding
+        assert (np.abs(U - U_ref) <= TOL_GRAD * aU + 1e-7 * aU + 1e-30).all(), np.abs(U - U_ref).max()
+
+
+def fd_coords(oc, b, coords, w, tau, h=1e-3):
+    x = b.astype(np.float64)
+    out = []
+    for v, i in coords:
+        xp = x.copy(); xp[v, i] += h
+        xm = x.copy(); xm[v, i] -= h
+        out.append(w[i] * (orc.relaxed_S(oc, xp, i, tau) - orc.relaxed_S(oc, xm, i, tau)) / (2 * h))
+    return np.array(out)
+
+
+def test_backward_vs_finite_differences(env):
+    torch, solver, ag = env
+    cnf = gen.planted_ksat(300, 1230, 3, seed=8)
+    solver.load(cnf)
+    oc = orc.Cnf.from_gen(cnf)
+    N = 64
+    rng = np.random.default_rng(9)
+    b = rng.integers(0, 2, size=(300, N)).astype(np.uint8)
+    w = rng.normal(size=N)
+    A = torch.tensor(b, dtype=torch.float32, device="cuda", requires_grad=True)
+    (ag.smoothmin_sat(A, solver, 1.0) * torch.tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
+    U = A.grad.cpu().numpy()
+    coords = [(int(v), int(i)) for v, i in zip(rng.integers(0, 300, 200), rng.integers(0, N, 200))]
+    fd = fd_coords(oc, b, coords, w, 1.0)
+    H = orc.histogram(oc, b)
+    _, table, _ = orc.smoothmin(H, 1.0, w)
+    U_ref = orc.adjoint(oc, b, table)
+    ref = np.array([U_ref[v, i] for v, i in coords])
+    got = np.array([U[v, i] for v, i in coords])
+    fd_err = np.abs(fd - ref)  # truncation error of the central difference (h = 1e-3)
+    assert fd_err.max() <= 1e-6 * np.abs(ref).max() + 1e-9
+    assert (np.abs(got - fd) <= 2 * fd_err + 1e-5 * np.abs(ref).max()).all()
+
+
+@pytest.mark.timeout(600)
+def test_structured_config_fd_and_oracle(env):
+    """The structured configuration at full size through the autograd Function:
+    sampled coordinates against central differences (h = 1e-3, FP64) of the
+    relaxed objective and against the oracle's adjoint."""
+    torch, solver, ag = env
+    cnf = gen.structured(500_000, 2_500_000, seed=2)
+    print("[autograd] structured config loaded", flush=True)
+    solver.load(cnf)
+    N = 128
+    th, _, _ = make_state(cnf.num_vars, N, 1002, t_moments=False)
+    b = (th > 0).astype(np.uint8)
+    rng = np.random.default_rng(2)
+    w = -np.ones(N)  # the loss of Eq. 3
+    A = torch.tensor(b, dtype=torch.float32, device="cuda", requires_grad=True)
+    (-ag.smoothmin_sat(A, solver, 1.0).sum()).backward()
+    U = A.grad.cpu().numpy()
+    oc = orc.Cnf.from_gen(cnf)
+    H = orc.histogram(oc, b)
+    _, table, _ = orc.smoothmin(H, 1.0)
+    deg = np.bincount(np.abs(cnf.lits) - 1, minlength=cnf.num_vars)
+    pick = np.unique(np.concatenate([rng.choice(cnf.num_vars, 24, replace=False), np.argsort(deg)[-2:]]))
+    osub = orc.Cnf.from_gen(sub_cnf(cnf, pick))
+    U_ref = orc.adjoint(osub, b, table)[pick]
+    aU = abs_adjoint(osub, b, table)[pick]
+    assert (np.abs(U[pick] - U_ref) <= TOL_GRAD * aU + 1e-30).all()
+    coords = [(int(v), int(rng.integers(0, N))) for v in pick[:12]]
+    got = np.array([U[v, i] for v, i in coords])
+    ref = np.array([U_ref[list(pick).index(v), i] for v, i in coords])
+    scale = np.abs(ref).max()
+    # h = 1e-3 (the configuration's step): the GPU is as close to the central
+    # difference as the FP64 oracle is, up to 1e-5 of the gradient scale
+    fd = fd_coords(oc, b, coords, w, 1.0, h=1e-3)
+    fd_err = np.abs(fd - ref)
+    assert fd_err.max() <= 1e-2 * scale  # O(h^2) truncation
+    assert (np.abs(got - fd) <= fd_err + 1e-5 * scale).all()
+    # a smaller step converges onto the adjoint
+    fd5 = fd_coords(oc, b, coords, w, 1.0, h=1e-5)
+    assert np.abs(fd5 - ref).max() <= 1e-5 * scale
+    assert (np.abs(got - fd5) <= 2e-5 * scale).all()
+
+
+def test_full_chain_gradient(env):
+    """theta -> Eq. 5 -> STE binarize -> layer -> Eq. 3: theta.grad vs the oracle g."""
+    torch, solver, ag = env
+    cnf = gen.planted_ksat(200, 800, 3, seed=1)
+    solver.load(cnf)
+    oc = orc.Cnf.from_gen(cnf)
+    th, _, _ = make_state(200, 64, 1001, t_moments=False, min_abs_mu=1e-2)
+    T = torch.tensor(th, device="cuda", requires_grad=True)
+    loss = ag.loss_of(T, solver, 1.0)
+    loss.backward()
+    ref = orc.step(oc, th.astype(np.float64), np.zeros((200, 64)), np.zeros((200, 64)), 0)
+    assert abs(loss.item() - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+    b, mu = orc.binarize(th.astype(np.float64))
+    _, table, _ = orc.smoothmin(orc.histogram(oc, b), 1.0)
+    ag_b = grad_bound(abs_adjoint(oc, b, table), th, mu, ref["g"])
+    g = T.grad.cpu().numpy()
+    assert (np.abs(g - ref["g"]) <= TOL_GRAD * ag_b + 1e-30).all(), np.abs(g - ref["g"]).max()
