@@ -61,6 +61,8 @@ def lib():
         L.orc_step.argtypes = [P, i32, P, i64, P, P, P, P, P, P, P, P, P]
         L.orc_relaxed_S.argtypes = [P, i32, P, i32, dbl]
         L.orc_relaxed_S.restype = dbl
+        L.orc_relaxed_fd.argtypes = [P, i32, P, i32, i32, dbl, dbl]
+        L.orc_relaxed_fd.restype = dbl
         L.orc_relaxed_loss.argtypes = [P, i32, P, dbl]
         L.orc_relaxed_loss.restype = dbl
         L.orc_extract_partial.argtypes = [P, i32, P, P, P, i32, i32, P, P, P]
@@ -230,6 +232,12 @@ def step(cnf: Cnf, theta, m, v, t: int, p: Params | None = None):
 def relaxed_S(cnf: Cnf, x: np.ndarray, i: int, tau: float = 1.0) -> float:
     x = np.ascontiguousarray(x, dtype=np.float64)
     return float(lib().orc_relaxed_S(cnf.handle, x.shape[1], _p(x), int(i), float(tau)))
+
+
+def relaxed_fd(cnf: Cnf, x: np.ndarray, v: int, i: int, h: float = 1e-3, tau: float = 1.0) -> float:
+    """(S~_i(x + h e_vi) - S~_i(x - h e_vi)) / (2h), free of cancellation in the column sums."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return float(lib().orc_relaxed_fd(cnf.handle, x.shape[1], _p(x), int(v), int(i), float(h), float(tau)))
 
 
 def relaxed_loss(cnf: Cnf, x: np.ndarray, tau: float = 1.0) -> float:

@@ -455,6 +455,53 @@ double orc_relaxed_S(const void *h, int32_t N, const double *x, int32_t i, doubl
     return num / den;
 }
 
+/* Central difference (S~_i(x + h e_vi) - S~_i(x - h e_vi)) / (2h) of the
+ * relaxed SmoothMin of candidate i, evaluated without cancelling the large
+ * column sums: with num = sum_c R~ w and den = sum_c w over all clauses
+ * (w = e^{-tau (R~ - m)}, m a fixed shift), only clauses containing v change,
+ * and S+ - S- = [num (dd- - dd+) + den (dn+ - dn-) + dn+ dd- - dn- dd+]
+ *              / [(den + dd+)(den + dd-)]. */
+double orc_relaxed_fd(const void *h, int32_t N, const double *x, int32_t v, int32_t i, double step, double tau)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (f->C == 0) return 0.0;
+    double m = INFINITY;
+    for (int64_t c = 0; c < f->C; ++c) {
+        double r = 0.0;
+        for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+            int32_t l = f->lit[q];
+            int32_t u = (l > 0 ? l : -l) - 1;
+            double xu = x[(int64_t)u * N + i];
+            r += (l > 0) ? xu : 1.0 - xu;
+        }
+        if (r < m) m = r;
+    }
+    m -= step; /* keep every shifted exponent non-positive */
+    double num = 0.0, den = 0.0, dnp = 0.0, ddp = 0.0, dnm = 0.0, ddm = 0.0;
+    for (int64_t c = 0; c < f->C; ++c) {
+        double r = 0.0, dr = 0.0;
+        for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+            int32_t l = f->lit[q];
+            int32_t u = (l > 0 ? l : -l) - 1;
+            double xu = x[(int64_t)u * N + i];
+            r += (l > 0) ? xu : 1.0 - xu;
+            if (u == v) dr += (l > 0) ? step : -step;
+        }
+        double w = exp(-tau * (r - m));
+        num += r * w;
+        den += w;
+        if (dr != 0.0) {
+            double wp = exp(-tau * (r + dr - m)), wm = exp(-tau * (r - dr - m));
+            dnp += (r + dr) * wp - r * w;
+            ddp += wp - w;
+            dnm += (r - dr) * wm - r * w;
+            ddm += wm - w;
+        }
+    }
+    double diff = (num * (ddm - ddp) + den * (dnp - dnm) + dnp * ddm - dnm * ddp) / ((den + ddp) * (den + ddm));
+    return diff / (2.0 * step);
+}
+
 /* Relaxed loss L~(x) = -sum_i S~_i (Eq. 3). */
 double orc_relaxed_loss(const void *h, int32_t N, const double *x, double tau)
 {

@@ -54,13 +54,9 @@ def test_forward_and_backward_vs_oracle(env):
 
 
 def fd_coords(oc, b, coords, w, tau, h=1e-3):
+    """Central differences of sum_i w_i S~_i(x) at the binary point b."""
     x = b.astype(np.float64)
-    out = []
-    for v, i in coords:
-        xp = x.copy(); xp[v, i] += h
-        xm = x.copy(); xm[v, i] -= h
-        out.append(w[i] * (orc.relaxed_S(oc, xp, i, tau) - orc.relaxed_S(oc, xm, i, tau)) / (2 * h))
-    return np.array(out)
+    return np.array([w[i] * orc.relaxed_fd(oc, x, v, i, h, tau) for v, i in coords])
 
 
 def test_backward_vs_finite_differences(env):
@@ -121,12 +117,8 @@ def test_structured_config_fd_and_oracle(env):
     # difference as the FP64 oracle is, up to 1e-5 of the gradient scale
     fd = fd_coords(oc, b, coords, w, 1.0, h=1e-3)
     fd_err = np.abs(fd - ref)
-    assert fd_err.max() <= 1e-2 * scale  # O(h^2) truncation
+    assert fd_err.max() <= 1e-5 * scale  # O(h^2) truncation of a smooth objective
     assert (np.abs(got - fd) <= fd_err + 1e-5 * scale).all()
-    # a smaller step converges onto the adjoint
-    fd5 = fd_coords(oc, b, coords, w, 1.0, h=1e-5)
-    assert np.abs(fd5 - ref).max() <= 1e-5 * scale
-    assert (np.abs(got - fd5) <= 2e-5 * scale).all()
 
 
 def test_full_chain_gradient(env):

@@ -252,6 +252,29 @@ def test_adjoint_is_exact_gradient_of_relaxed_loss(orc, tau):
         assert np.allclose(U, G, rtol=1e-6, atol=1e-9), np.abs(U - G).max()
 
 
+def test_relaxed_fd_matches_naive_central_difference(orc):
+    """The cancellation-free central difference equals the plain one where
+    the plain one is accurate (small instances), and both converge onto the
+    adjoint U as h -> 0."""
+    cnf = small_mixed_cnf()
+    oc = orc.Cnf.from_gen(cnf)
+    b, _ = orc.binarize(gen.normal_logits(6, 5, 3).astype(np.float64), orc.MODE_NONE)
+    x = b.astype(np.float64)
+    _, table, _ = orc.smoothmin(orc.histogram(oc, b), 1.3)
+    U = orc.adjoint(oc, b, table)
+    for v in range(6):
+        for i in range(5):
+            for h in (1e-2, 1e-3):
+                xp = x.copy(); xp[v, i] += h
+                xm = x.copy(); xm[v, i] -= h
+                naive = (orc.relaxed_S(oc, xp, i, 1.3) - orc.relaxed_S(oc, xm, i, 1.3)) / (2 * h)
+                assert orc.relaxed_fd(oc, x, v, i, h, 1.3) == pytest.approx(naive, rel=1e-9, abs=1e-12)
+            # -dS~/dx = U (Eq. 3 sign); O(h^2) convergence
+            e3 = abs(-orc.relaxed_fd(oc, x, v, i, 1e-3, 1.3) - U[v, i])
+            e4 = abs(-orc.relaxed_fd(oc, x, v, i, 1e-4, 1.3) - U[v, i])
+            assert e4 <= max(e3 / 50, 1e-13)
+
+
 def test_norm_backward_matches_fd(orc):
     """g = d/dtheta <U, theta / mean_row(theta)> with U held fixed (Eq. 5)."""
     g0 = np.random.default_rng(4)
