@@ -66,6 +66,11 @@ def lib():
         L.orc_relaxed_loss.argtypes = [P, i32, P, dbl]
         L.orc_relaxed_loss.restype = dbl
         L.orc_extract_partial.argtypes = [P, i32, P, P, P, i32, i32, P, P, P]
+        L.orc_features.argtypes = [P, P]
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_philox4x32_10.restype = None
+        L.orc_init_normal.argtypes = [i32, i32, ct.c_uint64, P]
+        L.orc_init_proposal.argtypes = [i32, i32, ct.c_uint64, P, i32, P]
         _lib = L
     return _lib
 
@@ -261,3 +266,34 @@ def extract_partial(cnf: Cnf, g, b, sat_count, max_cands: int, k: int):
 def default_k(num_vars: int) -> int:
     """k = 0.01% of the variables, at least 20 (Sec. IV-B)."""
     return max(20, -(-num_vars // 10000))
+
+
+NUM_FEATURES = 16
+
+
+def features(cnf: Cnf) -> np.ndarray:
+    """Per-variable features of the learned proposal, float64 [V][16] (reading R9)."""
+    X = np.empty((cnf.V, NUM_FEATURES), dtype=np.float64)
+    _check(lib().orc_features(cnf.handle, _p(X)), "features")
+    return X
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def init_normal(V: int, N: int, seed: int) -> np.ndarray:
+    th = np.empty((V, N), dtype=np.float32)
+    _check(lib().orc_init_normal(int(V), int(N), int(seed), _p(th)), "init_normal")
+    return th
+
+
+def init_proposal(p_true: np.ndarray, N: int, seed: int, mode: int = MODE_MEAN) -> np.ndarray:
+    p = np.ascontiguousarray(p_true, dtype=np.float32)
+    th = np.empty((p.size, N), dtype=np.float32)
+    _check(lib().orc_init_proposal(int(p.size), int(N), int(seed), _p(p), int(mode), _p(th)), "init_proposal")
+    return th

@@ -49,6 +49,22 @@
  *   R8  Partial extraction ranks variables by |g| where g is the gradient of
  *       the loss with respect to theta; variables that occur in no clause are
  *       skipped; ties go to the lower variable index.
+ *
+ * The learned proposal is not part of the paper; its definitions are this
+ * library's own and are written out here as plainly as the paper's:
+ *   R9  Per-variable features (orc_features) ignore tautological clauses.
+ *   R10 The random streams are Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ *       SC'11) with counter (e mod 2^32, e div 2^32, 0x5A17, 0) for element
+ *       e = v*N + i and key (seed mod 2^32, seed div 2^32); the N(0,1) draw is
+ *       Box-Muller on the first two output words, the Bernoulli draw compares
+ *       the third word with floor(p * 2^32).
+ *   R11 Initialisation from a proposal p_v (orc_init_proposal): b ~ Bern(p_v),
+ *       theta = +|z| where b = 1 and -|z| where b = 0 (z the N(0,1) draw of
+ *       the random initialisation).  In mean mode a row's negative entries are
+ *       scaled by min(1, 0.5 * (sum of its positive magnitudes) / (sum of its
+ *       negative magnitudes)) so that the row mean stays positive and Eq. 5
+ *       followed by Eq. 2 returns exactly b; a row with no b = 1 gets b = 1 at
+ *       candidate v mod N first (mean mode cannot represent an all-false row).
  */
 #include <math.h>
 #include <stdint.h>
@@ -563,5 +579,187 @@ int orc_extract_partial(const void *h, int32_t N, const double *g, const uint8_t
         }
     }
     free(occurs); free(order); free(taken);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned proposal: per-variable features (reading R9)                      */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_NF 16
+
+static int clause_is_tautology(const ocnf *f, int64_t c)
+{
+    for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q)
+        for (int64_t r = q + 1; r < f->off[c + 1]; ++r)
+            if (f->lit[q] == -f->lit[r]) return 1;
+    return 0;
+}
+
+/* X[v][16] = [log(1+pos_v), log(1+neg_v), (pos_v-neg_v)/max(1,deg_v),
+ *             (mean width of the clauses of v)/4 (0 when deg_v = 0),
+ *             h1[v][0..3], h2[v][0..3], h3[v][0..3]]
+ * with pos_v / neg_v the number of non-tautological clauses holding +v / -v,
+ * deg_v = pos_v + neg_v, and the signed neighbour aggregation
+ *   h0[v] = [(pos-neg)/max(1,deg), (pos-neg)/sqrt(max(1,deg)),
+ *            log(1+pos)-log(1+neg), 1]
+ *   h_r[v][ch] = (1/max(1,Z_v)) * sum over non-tautological clauses c, over the
+ *                literal l of c on v and every literal l' of c on another
+ *                variable u, of sgn(l) sgn(l') h_{r-1}[u][ch],
+ *   Z_v = number of such (c, l') pairs. */
+int orc_features(const void *h, double *X)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || !X) return ORC_E_ARG;
+    const int32_t V = f->V;
+    double *pos = (double *)calloc((size_t)(V > 0 ? V : 1), sizeof(double));
+    double *neg = (double *)calloc((size_t)(V > 0 ? V : 1), sizeof(double));
+    double *wsum = (double *)calloc((size_t)(V > 0 ? V : 1), sizeof(double));
+    double *Z = (double *)calloc((size_t)(V > 0 ? V : 1), sizeof(double));
+    double *hp = (double *)calloc((size_t)(V > 0 ? V : 1) * 4, sizeof(double));
+    double *hn = (double *)calloc((size_t)(V > 0 ? V : 1) * 4, sizeof(double));
+    uint8_t *taut = (uint8_t *)calloc((size_t)(f->C > 0 ? f->C : 1), 1);
+    if (!pos || !neg || !wsum || !Z || !hp || !hn || !taut) {
+        free(pos); free(neg); free(wsum); free(Z); free(hp); free(hn); free(taut);
+        return ORC_E_OOM;
+    }
+    for (int64_t c = 0; c < f->C; ++c) {
+        taut[c] = (uint8_t)clause_is_tautology(f, c);
+        if (taut[c]) continue;
+        int64_t k = f->off[c + 1] - f->off[c];
+        for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+            int32_t l = f->lit[q];
+            int32_t v = (l > 0 ? l : -l) - 1;
+            if (l > 0) pos[v] += 1.0; else neg[v] += 1.0;
+            wsum[v] += (double)k;
+            Z[v] += (double)(k - 1);
+        }
+    }
+    for (int32_t v = 0; v < V; ++v) {
+        double deg = pos[v] + neg[v];
+        double *x = X + (int64_t)v * ORC_NF;
+        x[0] = log(1.0 + pos[v]);
+        x[1] = log(1.0 + neg[v]);
+        x[2] = (pos[v] - neg[v]) / (deg > 1.0 ? deg : 1.0);
+        x[3] = deg > 0.0 ? wsum[v] / deg / 4.0 : 0.0;
+        hp[4 * v + 0] = x[2];
+        hp[4 * v + 1] = (pos[v] - neg[v]) / sqrt(deg > 1.0 ? deg : 1.0);
+        hp[4 * v + 2] = x[0] - x[1];
+        hp[4 * v + 3] = 1.0;
+    }
+    for (int r = 1; r <= 3; ++r) {
+        memset(hn, 0, sizeof(double) * 4 * (size_t)V);
+        for (int64_t c = 0; c < f->C; ++c) {
+            if (taut[c]) continue;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) {
+                int32_t l = f->lit[q];
+                int32_t v = (l > 0 ? l : -l) - 1;
+                for (int64_t e = f->off[c]; e < f->off[c + 1]; ++e) {
+                    int32_t l2 = f->lit[e];
+                    int32_t u = (l2 > 0 ? l2 : -l2) - 1;
+                    if (u == v) continue;
+                    double sg = ((l > 0) == (l2 > 0)) ? 1.0 : -1.0;
+                    for (int ch = 0; ch < 4; ++ch) hn[4 * v + ch] += sg * hp[4 * u + ch];
+                }
+            }
+        }
+        for (int32_t v = 0; v < V; ++v) {
+            double z = Z[v] > 1.0 ? Z[v] : 1.0;
+            for (int ch = 0; ch < 4; ++ch) {
+                hn[4 * v + ch] /= z;
+                X[(int64_t)v * ORC_NF + 4 * r + ch] = hn[4 * v + ch];
+            }
+        }
+        double *t = hp; hp = hn; hn = t;
+    }
+    free(pos); free(neg); free(wsum); free(Z); free(hp); free(hn); free(taut);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random streams and initialisation (readings R10, R11)                     */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x32 with 10 rounds: each round multiplies words 0 and 2 by the two
+ * published constants, swaps the high/low halves across the pairs and xors in
+ * the key, which is bumped by the two Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod_b = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(prod_b >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)prod_b;
+        uint32_t y2 = (uint32_t)(prod_a >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)prod_a;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static void draw(uint64_t seed, int64_t e, uint32_t w[4])
+{
+    uint32_t ctr[4] = {(uint32_t)e, (uint32_t)((uint64_t)e >> 32), 0x5A17u, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+/* N(0,1) by Box-Muller on two uniforms in (0,1), rounded to FP32. */
+static float box_muller(const uint32_t w[4])
+{
+    double u1 = ((double)w[0] + 0.5) / 4294967296.0;
+    double u2 = ((double)w[1] + 0.5) / 4294967296.0;
+    return (float)(sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2));
+}
+
+/* Random initialisation theta[v][i] ~ N(0,1) (Sec. IV-A), FP32. */
+int orc_init_normal(int32_t V, int32_t N, uint64_t seed, float *theta)
+{
+    if (V < 0 || N <= 0 || !theta) return ORC_E_ARG;
+    for (int64_t e = 0; e < (int64_t)V * N; ++e) {
+        uint32_t w[4];
+        draw(seed, e, w);
+        theta[e] = box_muller(w);
+    }
+    return ORC_OK;
+}
+
+/* Initialisation from a proposal p[v] = P(x_v = true) (reading R11). */
+int orc_init_proposal(int32_t V, int32_t N, uint64_t seed, const float *p, int32_t mode, float *theta)
+{
+    if (V < 0 || N <= 0 || !theta || (V > 0 && !p)) return ORC_E_ARG;
+    uint8_t *b = (uint8_t *)malloc((size_t)N);
+    float *a = (float *)malloc(sizeof(float) * (size_t)N);
+    if (!b || !a) { free(b); free(a); return ORC_E_OOM; }
+    for (int32_t v = 0; v < V; ++v) {
+        double pv = p[v];
+        if (!(pv >= 0.0)) pv = 0.0; /* NaN and negatives */
+        if (pv > 1.0) pv = 1.0;
+        double thr = floor(pv * 4294967296.0);
+        int any = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            uint32_t w[4];
+            draw(seed, (int64_t)v * N + i, w);
+            a[i] = fabsf(box_muller(w));
+            b[i] = ((double)w[2] < thr) ? 1 : 0;
+            any |= b[i];
+        }
+        double rho = 1.0;
+        if (mode == 1) {
+            if (!any) b[v % N] = 1;
+            double sp = 0.0, sn = 0.0;
+            for (int32_t i = 0; i < N; ++i) {
+                if (b[i]) sp += a[i]; else sn += a[i];
+            }
+            if (sn > 0.0 && 0.5 * sp / sn < 1.0) rho = 0.5 * sp / sn;
+        }
+        for (int32_t i = 0; i < N; ++i)
+            theta[(int64_t)v * N + i] = b[i] ? a[i] : (float)(-rho * (double)a[i]);
+    }
+    free(b); free(a);
     return ORC_OK;
 }
