@@ -11,6 +11,7 @@ resident in HBM before the timed region.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 10]
                        [--workload large|structured|tiny] [--no-cpu-baseline]
+                       [--calib-copy-mib M]
 """
 from __future__ import annotations
 
@@ -92,6 +93,9 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, launch one plain device copy kernel of this many MiB (read + write), "
+                         "the reference point for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding over candidates is "
@@ -156,6 +160,10 @@ def main():
         "best_sat_count": rep.best_sat_count,
         "first_sat_step": rep.first_sat_step,
     }
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        ms = s.copy_calibrate(nb)  # one copy kernel: nb bytes read, nb bytes written
+        out["calib_copy"] = {"bytes": nb, "ms": ms, "gbs": round(2 * nb / (ms * 1e-3) / 1e9, 1)}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(cnf, w, min(args.cpu_sample, N))

@@ -343,6 +343,13 @@ int32_t tsat_set_timing(tsat_solver* s, int32_t enable);
  * *iters = iterations averaged.  E_STATE if nothing was timed. */
 int32_t tsat_get_timing(tsat_solver* s, double* ms, int32_t* iters);
 
+/* Reference point for hardware byte counters: allocates two device buffers
+ * of `bytes` bytes (a multiple of 16, at least 16) on the solver's device,
+ * runs one plain coalesced copy kernel over them (bytes read + bytes
+ * written), frees them and returns its device time in *ms (may be NULL).
+ * E_OOM if the buffers cannot be allocated. */
+int32_t tsat_copy_calibrate(tsat_solver* s, int64_t bytes, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -135,6 +135,7 @@ hipError_t launch_expand(const uint64_t* bits, int64_t V, int W, int N, uint64_t
 hipError_t launch_pack(const float* assign, int V, int N, int W, uint64_t* out, int lit_rows, hipStream_t st);
 hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t st);
+hipError_t launch_copy16(void* dst, const void* src, int64_t n16, int blocks, hipStream_t st);
 hipError_t launch_rank(const int64_t* sat, int N, int32_t* order, hipStream_t st);
 hipError_t launch_select(const SelectArgs& a, int nblocks, hipStream_t st);
 

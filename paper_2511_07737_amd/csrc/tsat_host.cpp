@@ -380,7 +380,7 @@ static FwdGeom fwd_geometry(int32_t N, int32_t K1, int64_t Cb, int32_t KW)
     while (g.DT > 1 && (size_t)g.DT * 32 * bins * 4 > 64 * 1024) g.DT >>= 1;
     g.S = 256 / g.DT;
     g.tiles = (g.Dn + g.DT - 1) / g.DT;
-    static const int target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", 2048));
+    static const int target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", 1024));
     const int64_t target_x = std::max<int64_t>(1, (target_blocks + g.tiles - 1) / g.tiles);
     int64_t cpt = (Cb + (int64_t)g.S * target_x - 1) / ((int64_t)g.S * target_x);
     g.CPT = (int)std::max<int64_t>(16, std::min<int64_t>(255, cpt));
@@ -1490,6 +1490,35 @@ int32_t tsat_get_timing(tsat_solver* s, double* ms, int32_t* iters)
     if (s->timed_iters == 0) return fail(TSAT_E_STATE, "no timed iterations");
     for (int k = 0; k < 3; ++k) ms[k] = s->timed_ms[k];
     if (iters) *iters = s->timed_iters;
+    return TSAT_OK;
+}
+
+int32_t tsat_copy_calibrate(tsat_solver* s, int64_t bytes, double* ms)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (bytes < 16 || bytes % 16) return fail(TSAT_E_ARG, "bytes must be a positive multiple of 16");
+    RET(set_dev(s));
+    DBuf a, b;
+    RET(a.alloc((size_t)bytes, "copy source"));
+    RET(b.alloc((size_t)bytes, "copy destination"));
+    HIPCHK(launch_fill_u32(a.as<uint32_t>(), bytes / 4, 1u, s->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(TSAT_E_HIP, "hipEventCreate failed");
+    }
+    hipError_t err = hipEventRecord(e0, s->stream);
+    if (err == hipSuccess) err = launch_copy16(b.p, a.p, bytes / 16, 8 * s->cus, s->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(TSAT_E_HIP, "copy kernel failed: %s", hipGetErrorString(err));
+    if (ms) *ms = t;
     return TSAT_OK;
 }
 

@@ -896,6 +896,12 @@ __global__ void init_normal_kernel(float* __restrict__ theta, int64_t n, uint64_
     theta[e] = (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
 }
 
+__global__ void copy16_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) dst[e] = src[e];
+}
+
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t val)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1212,6 +1218,13 @@ hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(init_normal_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(void* dst, const void* src, int64_t n16, int blocks, hipStream_t st)
+{
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)dst, (const uint4*)src, n16);
     return hipGetLastError();
 }
 

@@ -121,6 +121,7 @@ _SIGS = [
     ("tsat_bwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_set_timing", _i32, [_P, _i32]),
     ("tsat_get_timing", _i32, [_P, ct.POINTER(_f64), ct.POINTER(_i32)]),
+    ("tsat_copy_calibrate", _i32, [_P, _i64, ct.POINTER(_f64)]),
 ]
 
 
@@ -403,6 +404,12 @@ class Solver:
         it = _i32()
         _check(lib().tsat_get_timing(self._h, ms, ct.byref(it)))
         return list(ms), int(it.value)
+
+    def copy_calibrate(self, nbytes: int) -> float:
+        """Run one plain device copy of nbytes (read + write); returns its ms."""
+        ms = _f64()
+        _check(lib().tsat_copy_calibrate(self._h, int(nbytes), ct.byref(ms)))
+        return float(ms.value)
 
 
 def pack_bits(values: np.ndarray) -> np.ndarray:
