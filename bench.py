@@ -66,6 +66,33 @@ def algorithmic_bytes_fwd(cnf, N):
     return 4 * cnf.num_lits + cnf.num_vars * W * 8
 
 
+KERNEL_SOURCES = ["paper_2511_07737_amd/csrc/tsat_kernels.hip", "paper_2511_07737_amd/csrc/tsat_device.h"]
+PROFILE_FILES = {"large": "profiles/var_pure_kernel__planted-3sat_V1e6_C4.1e6_N256.txt",
+                 "structured": "profiles/var_kernel__structured_V5e5_C2.5e6_N128.txt"}
+
+
+def measured_traffic(workload):
+    """HBM-side bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy
+    kernel), or None when there is none or the kernel sources changed since."""
+    import hashlib
+
+    path = PROFILE_FILES.get(workload)
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    fields = {}
+    for line in open(os.path.join(ROOT, path)):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cnf, w, n_sample):
     """The FP64 oracle step, single-threaded, on the same instance with
     n_sample of the candidates."""
@@ -92,7 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, launch one plain device copy kernel of this many MiB (read + write), "
                          "the reference point for scaling hardware byte counters")
@@ -135,7 +162,8 @@ def main():
     if dom_bytes is not None:
         achieved = dom_bytes / (kms[dom] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[dom],
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
+                    "kernel": names[dom],
                     "bytes_per_launch": dom_bytes}
     out = {
         "metric": "clause-literal evals/s (fwd+bwd, % HBM peak); steps-to-all-SAT learned vs random",

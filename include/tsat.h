@@ -330,6 +330,96 @@ int32_t tsat_fwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
 int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, const float* dS, float* U,
                      void* stream);
 
+/* --------------------------------------------------- learned proposal --- */
+/*
+ * A per-variable network proposes P(x_v = true) for every variable of the
+ * loaded CNF; the batch then starts from draws of that proposal instead of
+ * the N(0,1) logits of Sec. IV-A.  The network, its features and the
+ * proposal start are this library's extension, not part of the paper.
+ *
+ * Features (16 per variable, FP32), over the non-tautological clauses:
+ *   [0] log(1+pos_v)  [1] log(1+neg_v)  [2] (pos_v-neg_v)/max(1,deg_v)
+ *   [3] mean width of the clauses of v / 4 (0 if deg_v = 0)
+ *   [4+4(r-1) .. 7+4(r-1)] = h_r[v], r = 1..3, where
+ *   h_0[v] = ((pos-neg)/max(1,deg), (pos-neg)/sqrt(max(1,deg)),
+ *             log(1+pos)-log(1+neg), 1) and h_r[v] = (1/max(1,Z_v)) * sum
+ *   over clauses c of v and co-literals l' of c on another variable u of
+ *   sgn(l_v) sgn(l') h_{r-1}[u]; Z_v counts those (c, l') pairs.
+ * Network: a1 = bf16(X) bf16(W1) + b1, h1 = bf16(relu(a1)),
+ *   a2 = h1 bf16(W2) + b2, logit = relu(a2) bf16(w3) + b3; bf16() rounds to
+ *   nearest-even; products accumulate in FP32.  Parameters are one FP32
+ *   vector of TSAT_MLP_NUM_PARAMS values: W1 [16][128], b1 [128],
+ *   W2 [128][128], b2 [128], w3 [128], b3 [1] (W[in][out]).
+ */
+#define TSAT_MLP_FEATURES 16
+#define TSAT_MLP_HIDDEN 128
+#define TSAT_MLP_NUM_PARAMS 18817
+
+typedef struct tsat_mlp tsat_mlp;
+
+/* Features of the loaded CNF (all instances of a batch) into host X[V][16]. */
+int32_t tsat_get_features(tsat_solver* s, float* X);
+
+/* Same, into caller-owned device memory X[V][16] on `stream` (NULL: the
+ * null stream).  The call returns after enqueueing. */
+int32_t tsat_features_dev(tsat_solver* s, float* X, void* stream);
+
+/* Network handle on `device` with the given host parameters (required).
+ * Adam state starts at zero, step count 0.  E_HIP without a device. */
+int32_t tsat_mlp_create(int32_t device, const float* params, tsat_mlp** out);
+
+/* NULL-safe. */
+void tsat_mlp_destroy(tsat_mlp* m);
+
+/* Replace the parameters (host [TSAT_MLP_NUM_PARAMS]); resets Adam state
+ * and the step count. */
+int32_t tsat_mlp_set_params(tsat_mlp* m, const float* params);
+
+/* Copy the parameters to host memory. */
+int32_t tsat_mlp_get_params(tsat_mlp* m, float* params);
+
+/* Host copies of the gradient and loss of the last train step (either
+ * pointer may be NULL).  E_STATE before the first train step. */
+int32_t tsat_mlp_get_grad(tsat_mlp* m, float* grad, float* loss);
+
+/* Adam steps taken since creation or the last set_params. */
+int64_t tsat_mlp_step_count(const tsat_mlp* m);
+
+/* Forward of B rows of device X[B][16] (16-byte aligned): logits[B] and/or
+ * probs[B] = sigmoid(logit) (device, either may be NULL, not both), on
+ * `stream` (NULL: the null stream).  Returns after enqueueing. */
+int32_t tsat_mlp_forward_dev(tsat_mlp* m, const float* X, int64_t B, float* logits, float* probs, void* stream);
+
+/* One training step on B >= 1 device rows X[B][16], labels y[B] in {0,1}
+ * and optional weights w[B] (NULL: 1): the gradient of the weighted mean
+ * binary cross-entropy with logits, taken with the rounded tensors held
+ * fixed (the gradient of a master weight is that of its rounded copy; the
+ * relu of layer 1 passes where h1 > 0), summed in a fixed order; then, if
+ * lr > 0, one Adam step (beta 0.9/0.999, eps 1e-8, bias-corrected, 1-based
+ * step count).  lr <= 0 computes the gradient only.  Calls on one handle
+ * share its scratch: issue them in order on one stream.  Returns after
+ * enqueueing; tsat_mlp_get_grad synchronizes. */
+int32_t tsat_mlp_train_step_dev(tsat_mlp* m, const float* X, const float* y, const float* w, int64_t B, float lr,
+                                void* stream);
+
+/* Run the features and the network over the loaded CNF and keep
+ * p_v = sigmoid(logit_v) in the solver (optionally copied to host p[V]).
+ * The network must live on the solver's device. */
+int32_t tsat_propose(tsat_solver* s, tsat_mlp* m, float* p);
+
+/* Start a batch of N candidates from a proposal: p_true host [V] in [0,1]
+ * (values outside are clamped, NaN counts as 0), or NULL for the one kept by
+ * tsat_propose.  Candidate i of variable v draws b_vi = 1 with probability
+ * p_v and theta_vi = +|z_vi| if b_vi = 1, -|z_vi| otherwise, with z_vi the
+ * same N(0,1) draw tsat_init_batch(seed) makes (Philox4x32-10, counter
+ * (e mod 2^32, e div 2^32, 0x5A17, 0) for e = v N + i, key = seed; the
+ * Bernoulli draw compares the third output word with floor(p_v 2^32)).
+ * In mean mode (the solver's norm_mode) the negative entries of a row are
+ * scaled by min(1, 0.5 sum_{b=1}|z| / sum_{b=0}|z|) so that Eq. 5 followed
+ * by Eq. 2 reproduces b, and a row without b = 1 gets it at i = v mod N.
+ * Optimizer state and step count start at zero as in tsat_init_batch. */
+int32_t tsat_init_from_proposal(tsat_solver* s, int32_t N, uint64_t seed, const float* p_true);
+
 /* ------------------------------------------------------------ profiling --- */
 
 /* Enable (1) or disable (0) per-kernel HIP-event timing inside tsat_step.

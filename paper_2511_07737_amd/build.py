@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -12,8 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtsat.so")
 ARCH = os.environ.get("TSAT_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["tsat_kernels.hip"]
-HOST_SOURCES = ["tsat_host.cpp"]
+HIP_SOURCES = ["tsat_kernels.hip", "tsat_learned.hip"]
+HOST_SOURCES = ["tsat_host.cpp", "tsat_mlp.cpp"]
 # hipcc's host pass does not know this device feature and warns; harmless.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -29,16 +30,19 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "hipcc")
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
     common = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-result"]
+    jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        _run([hipcc, f"--offload-arch={ARCH}", *common, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append((obj, [hipcc, f"--offload-arch={ARCH}", *common, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src),
+                           "-o", obj]))
     for src in HOST_SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        _run([hipcc, *common, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append((obj, [hipcc, *common, "-c", os.path.join(CSRC, src), "-o", obj]))
+    # independent translation units: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(jobs), 4)) as ex:
+        list(ex.map(_run, [cmd for _, cmd in jobs]))
+    objs = [obj for obj, _ in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -17,95 +17,11 @@
 
 #include "tsat.h"
 #include "tsat_device.h"
+#include "tsat_host_util.h"
+#include "tsat_learned.h"
 
 using namespace tsat;
-
-// ---------------------------------------------------------------------------
-// errors
-// ---------------------------------------------------------------------------
-
-static thread_local std::string g_err;
-
-static int32_t fail(int32_t code, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-#define HIPCHK(x)                                                                            \
-    do {                                                                                     \
-        hipError_t e_ = (x);                                                                 \
-        if (e_ != hipSuccess) return fail(TSAT_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
-    } while (0)
-
-#define RET(x)                       \
-    do {                             \
-        int32_t r_ = (x);            \
-        if (r_ != TSAT_OK) return r_; \
-    } while (0)
-
-// allocation-failure injection for tests of the OOM path
-static int64_t g_fail_alloc_countdown = -2;
-
-static bool inject_alloc_failure()
-{
-    if (g_fail_alloc_countdown == -2) {
-        const char* e = getenv("TSAT_FAIL_ALLOC_AFTER");
-        g_fail_alloc_countdown = e ? atoll(e) : -1;
-    }
-    if (g_fail_alloc_countdown < 0) return false;
-    if (g_fail_alloc_countdown == 0) return true;
-    --g_fail_alloc_countdown;
-    return false;
-}
-
-// launch-shape knobs, overridable from the environment for tuning sweeps
-static int env_int(const char* name, int dflt)
-{
-    const char* e = getenv(name);
-    return e ? atoi(e) : dflt;
-}
-
-// ---------------------------------------------------------------------------
-// device buffers
-// ---------------------------------------------------------------------------
-
-struct DBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DBuf() = default;
-    DBuf(const DBuf&) = delete;
-    DBuf& operator=(const DBuf&) = delete;
-    ~DBuf() { release(); }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    int32_t alloc(size_t n, const char* what)
-    {
-        if (n == bytes && p) return TSAT_OK;
-        release();
-        if (n == 0) return TSAT_OK;
-        if (inject_alloc_failure()) return fail(TSAT_E_OOM, "device allocation of %zu bytes for %s failed (injected)", n, what);
-        if (hipMalloc(&p, n) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return fail(TSAT_E_OOM, "device allocation of %zu bytes for %s failed", n, what);
-        }
-        bytes = n;
-        return TSAT_OK;
-    }
-    // grow-only variant for scratch space
-    int32_t reserve(size_t n, const char* what) { return (n <= bytes && p) ? TSAT_OK : alloc(n, what); }
-    template <class T> T* as() const { return static_cast<T*>(p); }
-};
+using namespace tsat_host;
 
 // ---------------------------------------------------------------------------
 // host-side clause store (Sec. III-A; sparse P of Sec. IV-A)
@@ -324,6 +240,10 @@ struct tsat_solver {
     bool use_graph = false;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<char> graph_key;
+
+    // learned proposal: features and aggregation channels, kept proposal
+    DBuf feat, fh[2], fzinv, prop;
+    bool prop_valid = false;
 
     // timing
     bool timing = false;
@@ -771,6 +691,7 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     s->loaded = false;
     s->N = s->W = s->Np = 0;
     s->scr_Np = 0;
+    s->prop_valid = false;
     s->st = std::move(st);
     for (int k = 0; k <= s->st.K; ++k) {
         const auto& codes = s->st.buckets[k];
@@ -905,6 +826,112 @@ int32_t tsat_init_batch(tsat_solver* s, int32_t N, uint64_t seed, const float* i
     const size_t VN = (size_t)s->st.V * N;
     if (init_logits) HIPCHK(hipMemcpyAsync(s->theta.p, init_logits, VN * 4, hipMemcpyHostToDevice, s->stream));
     else HIPCHK(launch_init_normal(s->theta.as<float>(), (int64_t)VN, seed, s->stream));
+    RET(binarize_current(s, s->params.norm_mode));
+    RET(reset_ctrl(s, 0));
+    return TSAT_OK;
+}
+
+// Features of every variable of the loaded CNF into X[V][16] on stream st:
+// round 0 (counts, base features, h0), then three aggregation rounds.
+static int32_t enqueue_features(tsat_solver* s, float* X, hipStream_t st)
+{
+    const size_t V = (size_t)s->st.V;
+    RET(s->fh[0].reserve(V * sizeof(float4), "feature channels"));
+    RET(s->fh[1].reserve(V * sizeof(float4), "feature channels"));
+    RET(s->fzinv.reserve(V * sizeof(float), "feature normalizers"));
+    FeatArgs a{};
+    a.V = s->st.V;
+    a.pure_k = s->st.pure_k;
+    a.occ_off = s->occ_off.as<uint32_t>();
+    a.occ_mid = s->occ_mid.as<uint32_t>();
+    a.occ_data = s->occ_data.as<uint32_t>();
+    a.zinv = s->fzinv.as<float>();
+    a.X = X;
+    for (int r = 0; r <= 3; ++r) {
+        a.round = r;
+        a.h_prev = s->fh[(r + 1) & 1].as<float4>();
+        a.h_next = s->fh[r & 1].as<float4>();
+        HIPCHK(launch_features(a, st));
+    }
+    return TSAT_OK;
+}
+
+static int32_t need_loaded(tsat_solver* s)
+{
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
+    return set_dev(s);
+}
+
+int32_t tsat_get_features(tsat_solver* s, float* X)
+{
+    g_err.clear();
+    RET(need_loaded(s));
+    if (!X) return fail(TSAT_E_ARG, "X is NULL");
+    const size_t n = (size_t)s->st.V * kFeat;
+    RET(s->feat.reserve(n * sizeof(float), "features"));
+    RET(enqueue_features(s, s->feat.as<float>(), s->stream));
+    HIPCHK(hipMemcpyAsync(X, s->feat.p, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TSAT_OK;
+}
+
+int32_t tsat_features_dev(tsat_solver* s, float* X, void* stream)
+{
+    g_err.clear();
+    RET(need_loaded(s));
+    if (!X) return fail(TSAT_E_ARG, "X is NULL");
+    const hipStream_t st = (hipStream_t)stream; // NULL: the null (default) stream
+    // scratch channels are shared with the solver's stream: order both ways
+    HIPCHK(hipStreamSynchronize(s->stream));
+    RET(enqueue_features(s, X, st));
+    return TSAT_OK;
+}
+
+int32_t tsat_propose(tsat_solver* s, tsat_mlp* m, float* p)
+{
+    g_err.clear();
+    RET(need_loaded(s));
+    MlpDev d;
+    int32_t dev = -1;
+    RET(mlp_view(m, &d, &dev));
+    if (dev != s->device) return fail(TSAT_E_ARG, "the network lives on device %d, the solver on %d", dev, s->device);
+    const size_t V = (size_t)s->st.V;
+    RET(s->feat.reserve(V * kFeat * sizeof(float), "features"));
+    RET(s->prop.reserve(V * sizeof(float), "proposal"));
+    // the network's buffers are written by the null stream in its set-up calls
+    HIPCHK(hipDeviceSynchronize());
+    RET(enqueue_features(s, s->feat.as<float>(), s->stream));
+    HIPCHK(launch_mlp_forward(d, s->feat.as<float>(), (int64_t)V, nullptr, s->prop.as<float>(), s->stream));
+    if (p) HIPCHK(hipMemcpyAsync(p, s->prop.p, V * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->prop_valid = true;
+    return TSAT_OK;
+}
+
+int32_t tsat_init_from_proposal(tsat_solver* s, int32_t N, uint64_t seed, const float* p_true)
+{
+    g_err.clear();
+    RET(need_loaded(s));
+    if (N < 1 || N > TSAT_MAX_STEP_N) return fail(TSAT_E_ARG, "N must be in [1, %d] (got %d)", TSAT_MAX_STEP_N, N);
+    if (!p_true && !s->prop_valid) return fail(TSAT_E_STATE, "no proposal: pass p_true or call tsat_propose first");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const size_t V = (size_t)s->st.V;
+    if (p_true) {
+        RET(s->prop.reserve(V * sizeof(float), "proposal"));
+        HIPCHK(hipMemcpyAsync(s->prop.p, p_true, V * sizeof(float), hipMemcpyHostToDevice, s->stream));
+        s->prop_valid = true;
+    }
+    s->N = 0;
+    RET(alloc_batch(s, N));
+    PropArgs a{};
+    a.V = s->st.V;
+    a.N = N;
+    a.seed = seed;
+    a.mode = s->params.norm_mode;
+    a.p = s->prop.as<float>();
+    a.theta = s->theta.as<float>();
+    HIPCHK(launch_init_proposal(a, s->stream));
     RET(binarize_current(s, s->params.norm_mode));
     RET(reset_ctrl(s, 0));
     return TSAT_OK;

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include "tsat_device.h"
+#include "tsat_learned.h"
 
 namespace tsat {
 
@@ -885,15 +886,69 @@ __device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1
     }
 }
 
+// Element e of the batch draws one Philox block with counter
+// (e mod 2^32, e div 2^32, 0x5A17, 0) and key (seed mod 2^32, seed div 2^32):
+// words 0 and 1 give N(0,1) by Box-Muller, word 2 a Bernoulli draw.
+__device__ __forceinline__ float normal_draw(int64_t e, uint64_t seed, uint32_t* word2)
+{
+    uint32_t c[4] = {(uint32_t)e, (uint32_t)((uint64_t)e >> 32), 0x5A17u, 0u};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
+    const double u2 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
+    if (word2) *word2 = c[2];
+    return (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
 __global__ void init_normal_kernel(float* __restrict__ theta, int64_t n, uint64_t seed)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    uint32_t c[4] = {(uint32_t)e, (uint32_t)(e >> 32), 0x5A17u, 0u};
-    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double u1 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
-    const double u2 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
-    theta[e] = (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+    theta[e] = normal_draw(e, seed, nullptr);
+}
+
+// Initialisation from a proposal p_v = P(x_v = true), one wave per variable:
+// b_vi = [word2 < floor(p_v 2^32)], theta_vi = +|z_vi| where b_vi = 1 and
+// -rho_v |z_vi| where b_vi = 0, z_vi the draw of the random initialisation.
+// Mean mode (Eq. 5 ahead of Eq. 2) keeps the row mean positive so that the
+// normalised signs reproduce b: rho_v = min(1, 0.5 sum_{b=1}|z| / sum_{b=0}|z|),
+// and a row without any b = 1 gets b = 1 at candidate v mod N.
+__global__ __launch_bounds__(256) void init_proposal_kernel(PropArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t v = (int32_t)(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (v >= a.V) return;
+    const float pv = a.p[v];
+    double pd = pv >= 0.f ? (double)pv : 0.0; // NaN -> 0
+    if (pd > 1.0) pd = 1.0;
+    const double thr = floor(pd * 4294967296.0);
+    const int64_t e0 = (int64_t)v * a.N;
+    int forced = -1;
+    double rho = 1.0;
+    if (a.mode == 1) {
+        bool any = false;
+        for (int i = lane; i < a.N; i += 64) {
+            uint32_t w2;
+            (void)normal_draw(e0 + i, a.seed, &w2);
+            any |= (double)w2 < thr;
+        }
+        if (!ballot64(any)) forced = v % a.N;
+        double sp = 0.0, sn = 0.0;
+        for (int i = lane; i < a.N; i += 64) {
+            uint32_t w2;
+            const float mag = fabsf(normal_draw(e0 + i, a.seed, &w2));
+            if ((double)w2 < thr || i == forced) sp += (double)mag;
+            else sn += (double)mag;
+        }
+        sp = wave_sum(sp);
+        sn = wave_sum(sn);
+        if (sn > 0.0 && 0.5 * sp / sn < 1.0) rho = 0.5 * sp / sn;
+    }
+    for (int i = lane; i < a.N; i += 64) {
+        uint32_t w2;
+        const float mag = fabsf(normal_draw(e0 + i, a.seed, &w2));
+        const bool b = (double)w2 < thr || i == forced;
+        a.theta[e0 + i] = b ? mag : (float)(-rho * (double)mag);
+    }
 }
 
 __global__ void copy16_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n)
@@ -1225,6 +1280,13 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t n16, int blocks, hi
 {
     if (n16 <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)dst, (const uint4*)src, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_proposal(const PropArgs& a, hipStream_t st)
+{
+    if (a.V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(init_proposal_kernel, dim3((unsigned)((a.V + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -122,6 +122,18 @@ _SIGS = [
     ("tsat_set_timing", _i32, [_P, _i32]),
     ("tsat_get_timing", _i32, [_P, ct.POINTER(_f64), ct.POINTER(_i32)]),
     ("tsat_copy_calibrate", _i32, [_P, _i64, ct.POINTER(_f64)]),
+    ("tsat_get_features", _i32, [_P, _P]),
+    ("tsat_features_dev", _i32, [_P, _P, _P]),
+    ("tsat_mlp_create", _i32, [_i32, _P, ct.POINTER(_P)]),
+    ("tsat_mlp_destroy", None, [_P]),
+    ("tsat_mlp_set_params", _i32, [_P, _P]),
+    ("tsat_mlp_get_params", _i32, [_P, _P]),
+    ("tsat_mlp_get_grad", _i32, [_P, _P, _P]),
+    ("tsat_mlp_step_count", _i64, [_P]),
+    ("tsat_mlp_forward_dev", _i32, [_P, _P, _i64, _P, _P, _P]),
+    ("tsat_mlp_train_step_dev", _i32, [_P, _P, _P, _P, _i64, _f32, _P]),
+    ("tsat_propose", _i32, [_P, _P, _P]),
+    ("tsat_init_from_proposal", _i32, [_P, _i32, ct.c_uint64, _P]),
 ]
 
 
@@ -135,6 +147,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2511_07737_amd.build.build()")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one: whichever is loaded first serves the whole process, and torch
+        # does not see the GPU through the other.  Load torch's first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ct.CDLL(_LIB_PATH)
         for name, rt, args in _SIGS:
             f = getattr(L, name)
@@ -289,6 +308,29 @@ class Solver:
         _check(lib().tsat_init_batch(self._h, int(n), int(seed) & ((1 << 64) - 1), _ptr(lg)))
         self.N = int(n)
 
+    # learned proposal ---------------------------------------------------
+    def get_features(self) -> np.ndarray:
+        X = np.empty((self.V, MLP_FEATURES), dtype=np.float32)
+        _check(lib().tsat_get_features(self._h, _ptr(X)))
+        return X
+
+    def features_dev(self, X_ptr: int, stream: int | None = None) -> None:
+        _check(lib().tsat_features_dev(self._h, X_ptr, stream))
+
+    def propose(self, mlp: "Mlp", want_host: bool = True) -> np.ndarray | None:
+        p = np.empty(self.V, dtype=np.float32) if want_host else None
+        _check(lib().tsat_propose(self._h, mlp.handle, _ptr(p)))
+        return p
+
+    def init_from_proposal(self, n: int, seed: int = 0, p_true: np.ndarray | None = None) -> None:
+        pp = None
+        if p_true is not None:
+            pp = np.ascontiguousarray(p_true, dtype=np.float32)
+            if pp.shape != (self.V,):
+                raise ValueError(f"p_true must have shape {(self.V,)}")
+        _check(lib().tsat_init_from_proposal(self._h, int(n), int(seed) & ((1 << 64) - 1), _ptr(pp)))
+        self.N = int(n)
+
     # solving ------------------------------------------------------------
     def step(self, max_steps: int = 1, params: Params | None = None, stop_on_sat: bool = False,
              raise_numeric: bool = True) -> Report:
@@ -410,6 +452,69 @@ class Solver:
         ms = _f64()
         _check(lib().tsat_copy_calibrate(self._h, int(nbytes), ct.byref(ms)))
         return float(ms.value)
+
+
+MLP_FEATURES = 16
+MLP_HIDDEN = 128
+MLP_NUM_PARAMS = 18817
+
+
+class Mlp:
+    """The learned-proposal network on one device (see ``include/tsat.h``).
+    Device-pointer calls take raw addresses (e.g. ``tensor.data_ptr()``) and a
+    HIP stream handle (None: the null stream)."""
+
+    def __init__(self, params: np.ndarray, device: int = 0):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NUM_PARAMS,):
+            raise ValueError(f"params must have shape ({MLP_NUM_PARAMS},)")
+        h = _P()
+        _check(lib().tsat_mlp_create(int(device), _ptr(p), ct.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tsat_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: np.ndarray) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NUM_PARAMS,):
+            raise ValueError(f"params must have shape ({MLP_NUM_PARAMS},)")
+        _check(lib().tsat_mlp_set_params(self._h, _ptr(p)))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(MLP_NUM_PARAMS, dtype=np.float32)
+        _check(lib().tsat_mlp_get_params(self._h, _ptr(p)))
+        return p
+
+    def get_grad(self):
+        g = np.empty(MLP_NUM_PARAMS, dtype=np.float32)
+        loss = np.empty(1, dtype=np.float32)
+        _check(lib().tsat_mlp_get_grad(self._h, _ptr(g), _ptr(loss)))
+        return g, float(loss[0])
+
+    def step_count(self) -> int:
+        return int(lib().tsat_mlp_step_count(self._h))
+
+    def forward_dev(self, X_ptr: int, B: int, logits_ptr: int | None, probs_ptr: int | None,
+                    stream: int | None = None) -> None:
+        _check(lib().tsat_mlp_forward_dev(self._h, X_ptr, int(B), logits_ptr, probs_ptr, stream))
+
+    def train_step_dev(self, X_ptr: int, y_ptr: int, w_ptr: int | None, B: int, lr: float,
+                       stream: int | None = None) -> None:
+        _check(lib().tsat_mlp_train_step_dev(self._h, X_ptr, y_ptr, w_ptr, int(B), float(lr), stream))
 
 
 def pack_bits(values: np.ndarray) -> np.ndarray:
