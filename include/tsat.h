@@ -420,6 +420,40 @@ int32_t tsat_propose(tsat_solver* s, tsat_mlp* m, float* p);
  * Optimizer state and step count start at zero as in tsat_init_batch. */
 int32_t tsat_init_from_proposal(tsat_solver* s, int32_t N, uint64_t seed, const float* p_true);
 
+/* ------------------------------------------------------- launch shapes --- */
+
+/* Launch shapes of the step kernels.  They change how work is split over
+ * the GPU, never the arithmetic: results are identical under every shape. */
+typedef struct {
+    int32_t fwd_target_blocks; /* forward histogram: work units per launch to aim for (clause tile size
+                                  follows from it); default 1024 */
+    int32_t var_blocks_per_cu; /* fused update: persistent blocks per CU, 0 = 4 x occupancy */
+    int32_t pure_group;        /* uniform-width stores: occurrence records per load group, 1, 2 or 4 */
+    int32_t reserved;
+    double fwd_ms;             /* tsat_autotune output: forward time per iteration of the choice */
+    double var_ms;             /* tsat_autotune output: fused update time per iteration of the choice */
+} tsat_launch_config;
+
+/* Current launch shapes (fwd_ms/var_ms zero). */
+int32_t tsat_get_launch_config(tsat_solver* s, tsat_launch_config* out);
+
+/* Set launch shapes (fwd_ms/var_ms ignored); drops a captured graph.
+ * E_ARG outside the documented ranges.  The environment variables
+ * TSAT_FWD_TARGET_BLOCKS, TSAT_VAR_BLOCKS_PER_CU and TSAT_PURE_GROUP set the
+ * initial values of a new solver. */
+int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg);
+
+/* Autotuner: times candidate shapes on real iterations of the current batch
+ * (`iters` in [1, 64] iterations per candidate, per-kernel HIP-event timing):
+ * first the forward work-unit target (256..4096), then the fused update's
+ * blocks per CU (auto, 8, 16, 32, 64) with, for uniform-width stores, the
+ * record group (1, 2, 4); keeps the fastest of each and returns it in *best
+ * (may be NULL) with the measured times.  The iterations advance the batch
+ * (p as in tsat_step, no early stop); *iters_used (may be NULL) receives
+ * their number.  Callers that want a fresh start re-initialize the batch. */
+int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_launch_config* best,
+                      int32_t* iters_used);
+
 /* ------------------------------------------------------------ profiling --- */
 
 /* Enable (1) or disable (0) per-kernel HIP-event timing inside tsat_step.

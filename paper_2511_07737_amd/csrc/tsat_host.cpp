@@ -241,6 +241,11 @@ struct tsat_solver {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<char> graph_key;
 
+    // launch shapes (autotuned or set; environment overrides at creation)
+    int32_t fwd_target_blocks = 1024; // forward work units per launch to aim for
+    int32_t var_per_cu = 0;           // variable-major blocks per CU (0: 4 x occupancy)
+    int32_t pure_group = 2;           // records per load group, uniform-width stores
+
     // learned proposal: features and aggregation channels, kept proposal
     DBuf feat, fh[2], fzinv, prop;
     bool prop_valid = false;
@@ -291,7 +296,7 @@ struct FwdGeom {
     int DT, S, CPT, tiles, Dn;
 };
 
-static FwdGeom fwd_geometry(int32_t N, int32_t K1, int64_t Cb, int32_t KW)
+static FwdGeom fwd_geometry(int32_t N, int32_t K1, int64_t Cb, int32_t KW, int32_t target_blocks)
 {
     FwdGeom g;
     const int bins = (KW <= 4) ? KW + 1 : K1;
@@ -300,7 +305,7 @@ static FwdGeom fwd_geometry(int32_t N, int32_t K1, int64_t Cb, int32_t KW)
     while (g.DT > 1 && (size_t)g.DT * 32 * bins * 4 > 64 * 1024) g.DT >>= 1;
     g.S = 256 / g.DT;
     g.tiles = (g.Dn + g.DT - 1) / g.DT;
-    static const int target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", 1024));
+    target_blocks = std::max(1, target_blocks);
     const int64_t target_x = std::max<int64_t>(1, (target_blocks + g.tiles - 1) / g.tiles);
     int64_t cpt = (Cb + (int64_t)g.S * target_x - 1) / ((int64_t)g.S * target_x);
     g.CPT = (int)std::max<int64_t>(16, std::min<int64_t>(255, cpt));
@@ -340,7 +345,7 @@ static int32_t prepare_units(tsat_solver* s, int32_t N)
 {
     for (auto* b : s->buckets) {
         if (b->count == 0 || b->k == 0) continue;
-        const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k);
+        const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k, s->fwd_target_blocks);
         const FwdUnit* u;
         int n;
         RET(bucket_units(s, b, g, &u, &n));
@@ -355,7 +360,7 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
     const int32_t W = (N + 63) / 64;
     for (auto* b : s->buckets) {
         if (b->count == 0 || b->k == 0) continue;
-        const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k);
+        const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k, s->fwd_target_blocks);
         FwdArgs a{};
         int nunits = 0;
         RET(bucket_units(s, b, g, &a.units, &nunits));
@@ -404,8 +409,7 @@ static SminArgs smin_args(tsat_solver* s, const tsat_params& p, int32_t N, int32
 // resident round: waves that finish early pick up the remaining blocks).
 static int var_blocks(const tsat_solver* s, int32_t V, int occ = 0)
 {
-    static const int per_cu_env = env_int("TSAT_VAR_BLOCKS_PER_CU", 0);
-    const int per_cu = per_cu_env > 0 ? per_cu_env : (occ > 0 ? 4 * occ : 32);
+    const int per_cu = s->var_per_cu > 0 ? s->var_per_cu : (occ > 0 ? 4 * occ : 32);
     const int64_t want = ((int64_t)V + 3) / 4;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)s->cus * per_cu));
 }
@@ -420,8 +424,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.K1 = K1_of(s);
     a.mode = p.norm_mode;
     a.pure_k = s->st.pure_k;
-    static const int group = env_int("TSAT_PURE_GROUP", 2);
-    a.group = group;
+    a.group = s->pure_group;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
     a.occ_data = s->occ_data.as<uint32_t>();
@@ -652,6 +655,9 @@ int32_t tsat_create(const tsat_config* cfg, tsat_solver** out)
     if (hipSetDevice(dev) != hipSuccess) { delete s; return fail(TSAT_E_HIP, "hipSetDevice(%d) failed", dev); }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) s->cus = prop.multiProcessorCount;
+    s->fwd_target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", s->fwd_target_blocks));
+    s->var_per_cu = std::max(0, env_int("TSAT_VAR_BLOCKS_PER_CU", s->var_per_cu));
+    s->pure_group = env_int("TSAT_PURE_GROUP", s->pure_group);
     if (cfg && cfg->stream) {
         s->stream = (hipStream_t)cfg->stream;
     } else {
@@ -1501,6 +1507,117 @@ int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
 }
 
 // ------------------------------------------------------------------ timing
+
+static int32_t check_launch_config(const tsat_launch_config* c)
+{
+    if (c->fwd_target_blocks < 1 || c->fwd_target_blocks > (1 << 20))
+        return fail(TSAT_E_ARG, "fwd_target_blocks must be in [1, 2^20]");
+    if (c->var_blocks_per_cu < 0 || c->var_blocks_per_cu > 1024)
+        return fail(TSAT_E_ARG, "var_blocks_per_cu must be in [0, 1024]");
+    if (c->pure_group != 1 && c->pure_group != 2 && c->pure_group != 4)
+        return fail(TSAT_E_ARG, "pure_group must be 1, 2 or 4");
+    return TSAT_OK;
+}
+
+int32_t tsat_get_launch_config(tsat_solver* s, tsat_launch_config* out)
+{
+    g_err.clear();
+    if (!s || !out) return fail(TSAT_E_ARG, "NULL argument");
+    memset(out, 0, sizeof *out);
+    out->fwd_target_blocks = s->fwd_target_blocks;
+    out->var_blocks_per_cu = s->var_per_cu;
+    out->pure_group = s->pure_group;
+    return TSAT_OK;
+}
+
+int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg)
+{
+    g_err.clear();
+    if (!s || !cfg) return fail(TSAT_E_ARG, "NULL argument");
+    RET(check_launch_config(cfg));
+    RET(set_dev(s));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->drop_graph();
+    s->fwd_target_blocks = cfg->fwd_target_blocks;
+    s->var_per_cu = cfg->var_blocks_per_cu;
+    s->pure_group = cfg->pure_group;
+    return TSAT_OK;
+}
+
+// Time `iters` eager iterations under the current launch shape; per-kernel
+// averages (forward, SmoothMin, fused update) in ms.
+static int32_t time_iterations(tsat_solver* s, int32_t iters, const tsat_params* p, double ms[3])
+{
+    const bool timing = s->timing, graph = s->use_graph;
+    s->timing = true;
+    s->use_graph = false;
+    tsat_report rep;
+    const int32_t rc = tsat_step(s, iters, p, 0, &rep);
+    s->timing = timing;
+    s->use_graph = graph;
+    if (rc != TSAT_OK) return rc;
+    if (s->timed_iters == 0) return fail(TSAT_E_STATE, "no timed iterations");
+    for (int k = 0; k < 3; ++k) ms[k] = s->timed_ms[k];
+    return TSAT_OK;
+}
+
+int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_launch_config* best,
+                      int32_t* iters_used)
+{
+    g_err.clear();
+    RET(need_batch(s));
+    if (iters < 1 || iters > 64) return fail(TSAT_E_ARG, "iters must be in [1, 64]");
+    int32_t used = 0;
+    double ms[3];
+    tsat_launch_config cur;
+    RET(tsat_get_launch_config(s, &cur));
+    // forward work-unit target: only the forward kernels depend on it
+    static const int kFwd[] = {256, 512, 1024, 2048, 4096};
+    double best_fwd = 1e30;
+    int pick_fwd = cur.fwd_target_blocks;
+    for (int f : kFwd) {
+        tsat_launch_config c = cur;
+        c.fwd_target_blocks = f;
+        RET(tsat_set_launch_config(s, &c));
+        RET(prepare_units(s, s->N));
+        RET(time_iterations(s, iters, p, ms));
+        used += iters;
+        if (ms[0] < best_fwd) {
+            best_fwd = ms[0];
+            pick_fwd = f;
+        }
+    }
+    cur.fwd_target_blocks = pick_fwd;
+    // fused update kernel: blocks per CU, and the record grouping of
+    // uniform-width stores
+    static const int kPerCu[] = {0, 8, 16, 32, 64};
+    const bool pure = s->st.pure_k != 0;
+    static const int kGroups[] = {1, 2, 4};
+    double best_var = 1e30;
+    tsat_launch_config pick = cur;
+    for (int pc : kPerCu) {
+        for (int gi = 0; gi < (pure ? 3 : 1); ++gi) {
+            tsat_launch_config c = cur;
+            c.var_blocks_per_cu = pc;
+            c.pure_group = pure ? kGroups[gi] : cur.pure_group;
+            RET(tsat_set_launch_config(s, &c));
+            RET(time_iterations(s, iters, p, ms));
+            used += iters;
+            if (ms[2] < best_var) {
+                best_var = ms[2];
+                pick = c;
+            }
+        }
+    }
+    RET(tsat_set_launch_config(s, &pick));
+    if (best) {
+        *best = pick;
+        best->fwd_ms = best_fwd;
+        best->var_ms = best_var;
+    }
+    if (iters_used) *iters_used = used;
+    return TSAT_OK;
+}
 
 int32_t tsat_set_timing(tsat_solver* s, int32_t enable)
 {

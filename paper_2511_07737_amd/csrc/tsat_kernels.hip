@@ -559,6 +559,23 @@ __device__ __forceinline__ VarInst var_instance(const VarArgs& a, uint32_t v)
     return r;
 }
 
+template <int OP>
+__device__ __forceinline__ VarInst instance_state(const VarArgs& a, uint32_t inst)
+{
+    VarInst r;
+    r.inst = inst;
+    r.frozen = false;
+    r.witness = 0;
+    r.wcand = 0;
+    if (OP == OP_STEP && a.ictrl) {
+        const InstCtrl* ic = a.ictrl + inst;
+        r.frozen = sload(&ic->frozen) != 0;
+        r.witness = sload(&ic->witness_pending);
+        r.wcand = sload(&ic->sat_cand);
+    }
+    return r;
+}
+
 // The update kernel advances the iteration index once all of it has run
 // (the next kernel on the stream sees it).
 __device__ __forceinline__ void advance_step(const VarArgs& a)
@@ -691,6 +708,80 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
 // n_O = c_O - c_{O+1} (c_0 = degree) and
 // U = sum_O n+_O g[x + O] - sum_O n-_O g[1 - x + O], x the candidate's own
 // value.  The dL/dR table of the lane's candidates sits in registers.
+// ---------------------------------------------------------------------------
+// Batched scalar-memory gathers.  Scalar loads return out of order, so a
+// wave can only wait for all of its outstanding ones at once; the gather of
+// a variable's occurrence records is therefore cut into as few batches as
+// the scalar registers allow, each one inline-assembly statement that issues
+// its loads and waits inside it (the compiler can neither re-issue the loads
+// later nor read their registers before they arrive).
+// ---------------------------------------------------------------------------
+
+typedef uint32_t sv2 __attribute__((ext_vector_type(2)));
+typedef uint32_t sv4 __attribute__((ext_vector_type(4)));
+typedef uint32_t sv8 __attribute__((ext_vector_type(8)));
+typedef uint32_t sv16 __attribute__((ext_vector_type(16)));
+
+// scalar registers holding the first J 64-bit words of a literal row
+template <int J> struct RowVec;
+template <> struct RowVec<1> { typedef sv2 T; };
+template <> struct RowVec<2> { typedef sv4 T; };
+template <> struct RowVec<4> { typedef sv8 T; };
+
+#define TSAT_ROWS8(OPC)                                                                                      \
+    asm volatile(OPC " %0, %8, %9\n\t" OPC " %1, %8, %10\n\t" OPC " %2, %8, %11\n\t" OPC " %3, %8, %12\n\t" \
+                 OPC " %4, %8, %13\n\t" OPC " %5, %8, %14\n\t" OPC " %6, %8, %15\n\t" OPC " %7, %8, %16\n\t" \
+                 "s_waitcnt lgkmcnt(0)"                                                                      \
+                 : "=&s"(r[0]), "=&s"(r[1]), "=&s"(r[2]), "=&s"(r[3]), "=&s"(r[4]), "=&s"(r[5]), "=&s"(r[6]),   \
+                   "=&s"(r[7])                                                                               \
+                 : "s"(base), "s"(off[0]), "s"(off[1]), "s"(off[2]), "s"(off[3]), "s"(off[4]), "s"(off[5]),     \
+                   "s"(off[6]), "s"(off[7]))
+
+// eight literal rows at byte offsets off[] from base, in one round trip
+template <int J>
+__device__ __forceinline__ void smem_rows8(uint64_t base, const uint32_t (&off)[8], typename RowVec<J>::T (&r)[8])
+{
+    if constexpr (J == 1) TSAT_ROWS8("s_load_dwordx2");
+    else if constexpr (J == 2) TSAT_ROWS8("s_load_dwordx4");
+    else TSAT_ROWS8("s_load_dwordx8");
+}
+#undef TSAT_ROWS8
+
+// sixteen words at byte offset off from base, in one round trip
+__device__ __forceinline__ sv16 smem_words16(uint64_t base, uint32_t off)
+{
+    sv16 r;
+    asm volatile("s_load_dwordx16 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=&s"(r) : "s"(base), "s"(off));
+    return r;
+}
+
+// The first sixteen code words of a variable's positive and negative
+// records, and the record offsets of the next variable, in one round trip.
+// Also the FP64 row mean of the variable and the instance index of the next
+// variable, so that no other scalar round trip precedes the record batches.
+__device__ __forceinline__ void smem_var_start(uint64_t occ, uint32_t off_pos, uint32_t off_neg, uint64_t offs,
+                                               uint64_t mids, uint32_t off_next, uint64_t mu_base, uint32_t off_mu,
+                                               uint64_t inst_base, sv16& cp, sv16& cn, sv2& rn, uint32_t& mn,
+                                               sv2& mu, uint32_t& inst_next)
+{
+    asm volatile("s_load_dwordx16 %0, %6, %7\n\t"
+                 "s_load_dwordx16 %1, %6, %8\n\t"
+                 "s_load_dwordx2 %2, %9, %11\n\t"
+                 "s_load_dword %3, %10, %11\n\t"
+                 "s_load_dwordx2 %4, %12, %13\n\t"
+                 "s_load_dword %5, %14, %11\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&s"(cp), "=&s"(cn), "=&s"(rn), "=&s"(mn), "=&s"(mu), "=&s"(inst_next)
+                 : "s"(occ), "s"(off_pos), "s"(off_neg), "s"(offs), "s"(mids), "s"(off_next), "s"(mu_base),
+                   "s"(off_mu), "s"(inst_base));
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t row_word(const typename RowVec<J>::T& r, int j)
+{
+    return (uint64_t)r[2 * j] | ((uint64_t)r[2 * j + 1] << 32);
+}
+
 template <int KO>
 __device__ __forceinline__ void cum_masks(const uint64_t (&w)[KO], uint64_t (&ge)[KO])
 {
@@ -722,11 +813,42 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
     float gt[K1][J];
     uint32_t gt_inst = 0xffffffffu;
     int bad = 0;
+    // G = 4 selects the batched scalar-memory gather (rows of up to four words)
+    constexpr bool BATCHED = G == 4 && J <= 4;
+    const uint64_t lit_u64 = uniform64((uint64_t)a.lits_cur);
+    const uint64_t occ_base = uniform64((uint64_t)a.occ_data);
+    const uint64_t offs_base = uniform64((uint64_t)a.occ_off);
+    const uint64_t mids_base = uniform64((uint64_t)a.occ_mid);
+    // record offsets and instance of the wave's current variable (prefetched
+    // one variable ahead), and the state of the last instance seen
+    uint32_t b_r0 = 0, b_rm = 0, b_r1 = 0, b_inst = 0;
+    const uint64_t mu_base = uniform64((uint64_t)(a.mu_cur ? a.mu_cur : (const double*)a.occ_off));
+    const uint64_t inst_base = uniform64((uint64_t)(a.var_inst ? a.var_inst : a.occ_mid));
+    VarInst vic = instance_state<OP>(a, 0u);
+    if (BATCHED && wave0 < (uint32_t)a.V) {
+        b_r0 = sload(a.occ_off + wave0);
+        b_rm = sload(a.occ_mid + wave0);
+        b_r1 = sload(a.occ_off + wave0 + 1);
+        b_inst = a.var_inst ? sload(a.var_inst + wave0) : 0u;
+    }
 
     for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
-        const VarInst vi = var_instance<OP>(a, v);
+        VarInst vi;
+        if constexpr (BATCHED) {
+            if (a.var_inst && b_inst != vic.inst) vic = instance_state<OP>(a, b_inst);
+            vi = vic;
+        } else {
+            vi = var_instance<OP>(a, v);
+        }
         if (vi.frozen) {
             keep_variable<J>(a, v, lane);
+            if (BATCHED) {
+                const uint32_t vn = min(v + nwaves, (uint32_t)a.V - 1u);
+                b_r0 = sload(a.occ_off + vn);
+                b_rm = sload(a.occ_mid + vn);
+                b_r1 = sload(a.occ_off + vn + 1);
+                b_inst = a.var_inst ? sload(a.var_inst + vn) : 0u;
+            }
             continue;
         }
         if (vi.inst != gt_inst) {
@@ -742,11 +864,21 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
         bool valid[J];
         load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
         bool clamped = false;
-        const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+        const bool need_mu = !(OP == OP_ADJ || a.mode != 1);
+        double mu = 1.0;
+        if (!BATCHED && need_mu) mu = clamp_mu(sload(a.mu_cur + v), clamped);
         const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
         uint64_t oP[J];
+        if constexpr (BATCHED) {
+            // the own row through the vector path, off the scalar round trips
+            uint32_t zv;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zv));
 #pragma unroll
-        for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+            for (int j = 0; j < J; ++j) oP[j] = ownp[j + zv];
+        } else {
+#pragma unroll
+            for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+        }
         uint32_t cnt[2][KO][J];
 #pragma unroll
         for (int sg = 0; sg < 2; ++sg)
@@ -754,7 +886,63 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
             for (int o = 0; o < KO; ++o)
 #pragma unroll
                 for (int j = 0; j < J; ++j) cnt[sg][o][j] = 0;
-        const uint32_t r0 = sload(a.occ_off + v), rm = sload(a.occ_mid + v), r1 = sload(a.occ_off + v + 1);
+        const uint32_t r0 = BATCHED ? b_r0 : sload(a.occ_off + v);
+        const uint32_t rm = BATCHED ? b_rm : sload(a.occ_mid + v);
+        const uint32_t r1 = BATCHED ? b_r1 : sload(a.occ_off + v + 1);
+        if constexpr (BATCHED) {
+            // record counts per chunk of code words and per batch of eight rows
+            constexpr int RPC = 16 / KO, RB = 8 / KO;
+            const uint32_t vn = min(v + nwaves, (uint32_t)a.V - 1u);
+            sv16 cfirst[2];
+            sv2 rn, mub;
+            uint32_t mn, inst_n;
+            smem_var_start(occ_base, r0 * (uint32_t)(4 * KO), rm * (uint32_t)(4 * KO), offs_base, mids_base,
+                           vn * 4u, mu_base, need_mu ? v * 8u : 0u, inst_base, cfirst[0], cfirst[1], rn, mn, mub,
+                           inst_n);
+            if (need_mu)
+                mu = clamp_mu(__longlong_as_double((long long)((uint64_t)mub[0] | ((uint64_t)mub[1] << 32))),
+                              clamped);
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const uint32_t beg = sg ? rm : r0, end = sg ? r1 : rm;
+                for (uint32_t c0 = beg; c0 < end; c0 += RPC) {
+                    const sv16 ck = (c0 == beg) ? cfirst[sg] : smem_words16(occ_base, c0 * (uint32_t)(4 * KO));
+#pragma unroll
+                    for (int b = 0; b < (RPC + RB - 1) / RB; ++b) {
+                        const uint32_t q0 = c0 + (uint32_t)(b * RB);
+                        if (q0 >= end) break; // wave-uniform
+                        uint32_t off[8];
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            const int rec = b * RB + t / KO;
+                            const bool use = t < RB * KO && rec < RPC && q0 + (uint32_t)(t / KO) < end;
+                            off[t] = use ? ck[rec * KO + t % KO] * row_bytes : 0u;
+                        }
+                        typename RowVec<J>::T rows[8];
+                        smem_rows8<J>(lit_u64, off, rows);
+#pragma unroll
+                        for (int g = 0; g < RB; ++g) {
+                            const bool live = b * RB + g < RPC && q0 + (uint32_t)g < end; // wave-uniform
+#pragma unroll
+                            for (int j = 0; j < J; ++j) {
+                                uint64_t wj[KO], ge[KO];
+#pragma unroll
+                                for (int e = 0; e < KO; ++e) wj[e] = row_word<J>(rows[g * KO + e], j);
+                                cum_masks<KO>(wj, ge);
+#pragma unroll
+                                for (int o = 0; o < KO; ++o)
+                                    cnt[sg][o][j] = add_lane_bit(cnt[sg][o][j], live ? ge[o] : 0ull);
+                            }
+                        }
+                    }
+                }
+            }
+            b_r0 = rn[0];
+            b_r1 = rn[1];
+            b_rm = mn;
+            b_inst = a.var_inst ? inst_n : 0u;
+        }
+        if constexpr (!BATCHED) {
 #pragma unroll
         for (int sg = 0; sg < 2; ++sg) {
             const uint32_t beg = sg ? rm : r0, end = sg ? r1 : rm;
@@ -799,11 +987,13 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
                 }
             }
         }
+        }
         const uint32_t dp = rm - r0, dn = r1 - rm;
         double U[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const uint32_t x = add_lane_bit(0u, oP[j]); // own value of this lane's candidate
+            // own value of this lane's candidate
+            const uint32_t x = BATCHED ? (uint32_t)(oP[j] >> lane) & 1u : add_lane_bit(0u, oP[j]);
             float u = 0.f;
 #pragma unroll
             for (int O = 0; O <= KO; ++O) {

@@ -252,13 +252,16 @@ def ragged_set(
 ) -> list[CNF]:
     """Planted k-SAT instances with V log-uniform in [vmin, vmax] and ratio uniform
     in [ratio_lo, ratio_hi]; instance j uses seed ``seed + j``."""
-    out = []
-    for j in range(count):
-        g = rng(seed + j)
-        V = int(round(math.exp(g.uniform(math.log(vmin), math.log(vmax)))))
-        C = int(round(g.uniform(ratio_lo, ratio_hi) * V))
-        out.append(planted_ksat(V, C, k=k, seed=(seed + j) * 7919 + 1))
-    return out
+    return [ragged_instance(j, seed, vmin, vmax, ratio_lo, ratio_hi, k) for j in range(count)]
+
+
+def ragged_instance(j: int, seed: int = 3000, vmin: int = 1000, vmax: int = 200000, ratio_lo: float = 3.8,
+                    ratio_hi: float = 4.2, k: int = 3) -> CNF:
+    """Instance j of ``ragged_set`` (drawn on its own, so sets can be built in parallel)."""
+    g = rng(seed + j)
+    V = int(round(math.exp(g.uniform(math.log(vmin), math.log(vmax)))))
+    C = int(round(g.uniform(ratio_lo, ratio_hi) * V))
+    return planted_ksat(V, C, k=k, seed=(seed + j) * 7919 + 1)
 
 
 def normal_logits(num_vars: int, n: int, seed: int) -> np.ndarray:

@@ -32,6 +32,14 @@ class TsatError(RuntimeError):
         self.code = code
 
 
+class LaunchConfig(ct.Structure):
+    _fields_ = [("fwd_target_blocks", ct.c_int32), ("var_blocks_per_cu", ct.c_int32), ("pure_group", ct.c_int32),
+                ("reserved", ct.c_int32), ("fwd_ms", ct.c_double), ("var_ms", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class Params(ct.Structure):
     _fields_ = [
         ("tau", _f64), ("lr0", _f64), ("lr_decay", _f64), ("lr_min", _f64),
@@ -122,6 +130,9 @@ _SIGS = [
     ("tsat_set_timing", _i32, [_P, _i32]),
     ("tsat_get_timing", _i32, [_P, ct.POINTER(_f64), ct.POINTER(_i32)]),
     ("tsat_copy_calibrate", _i32, [_P, _i64, ct.POINTER(_f64)]),
+    ("tsat_get_launch_config", _i32, [_P, ct.POINTER(LaunchConfig)]),
+    ("tsat_set_launch_config", _i32, [_P, ct.POINTER(LaunchConfig)]),
+    ("tsat_autotune", _i32, [_P, _i32, _P, ct.POINTER(LaunchConfig), ct.POINTER(_i32)]),
     ("tsat_get_features", _i32, [_P, _P]),
     ("tsat_features_dev", _i32, [_P, _P, _P]),
     ("tsat_mlp_create", _i32, [_i32, _P, ct.POINTER(_P)]),
@@ -307,6 +318,30 @@ class Solver:
                 raise ValueError(f"init_logits must have shape {(self.V, n)}")
         _check(lib().tsat_init_batch(self._h, int(n), int(seed) & ((1 << 64) - 1), _ptr(lg)))
         self.N = int(n)
+
+    # launch shapes -------------------------------------------------------
+    def launch_config(self) -> LaunchConfig:
+        c = LaunchConfig()
+        _check(lib().tsat_get_launch_config(self._h, ct.byref(c)))
+        return c
+
+    def set_launch_config(self, fwd_target_blocks=None, var_blocks_per_cu=None, pure_group=None) -> None:
+        c = self.launch_config()
+        if fwd_target_blocks is not None:
+            c.fwd_target_blocks = int(fwd_target_blocks)
+        if var_blocks_per_cu is not None:
+            c.var_blocks_per_cu = int(var_blocks_per_cu)
+        if pure_group is not None:
+            c.pure_group = int(pure_group)
+        _check(lib().tsat_set_launch_config(self._h, ct.byref(c)))
+
+    def autotune(self, iters: int = 3, params: Params | None = None):
+        """Pick the fastest launch shapes on real iterations; returns (config, iterations used)."""
+        c = LaunchConfig()
+        used = _i32()
+        _check(lib().tsat_autotune(self._h, int(iters), ct.byref(params) if params is not None else None,
+                                   ct.byref(c), ct.byref(used)))
+        return c, int(used.value)
 
     # learned proposal ---------------------------------------------------
     def get_features(self) -> np.ndarray:

@@ -1,0 +1,50 @@
+"""Host-side pieces of the ragged batch and the learned-proposal pipeline."""
+import numpy as np
+
+from paper_2511_07737_amd import gen, learned, ragged, tsat
+
+
+def test_parallel_generation_matches_sequential():
+    a = ragged.generate(24, seed=11, vmin=100, vmax=3000, workers=4)
+    b = gen.ragged_set(24, seed=11, vmin=100, vmax=3000)
+    assert all(x.num_vars == y.num_vars and np.array_equal(x.lits, y.lits) for x, y in zip(a, b))
+    sizes = [c.num_vars for c in b]
+    assert min(sizes) >= 100 and max(sizes) <= 3000
+    ratios = [c.num_clauses / c.num_vars for c in b]
+    assert 3.79 <= min(ratios) and max(ratios) <= 4.21
+
+
+def test_host_witness_check():
+    c = gen.planted_ksat(500, 2100, 3, seed=3)
+    assert ragged.satisfies(c, c.planted)
+    flipped = c.planted.copy()
+    flipped[:] = 1 - flipped
+    assert not ragged.satisfies(c, flipped)
+    assert not ragged.satisfies(gen.CNF.from_clauses(3, [[1], []]), np.ones(3, np.uint8))
+    assert ragged.satisfies(gen.CNF.from_clauses(3, []), np.zeros(3, np.uint8))
+
+
+def test_column_bits_matches_pack_helpers():
+    g = np.random.default_rng(2)
+    b = g.integers(0, 2, size=(50, 130)).astype(np.uint8)
+    p = tsat.pack_bits(b)
+    for cand in (0, 63, 64, 129):
+        assert np.array_equal(learned.column_bits(p, cand), b[:, cand])
+
+
+def test_corpus_and_parameter_layout():
+    cs = learned.corpus(6, vmin=1000, vmax=2000, workers=2)
+    assert [c.num_vars for c in cs] == [c.num_vars for c in learned.corpus(6, vmin=1000, vmax=2000, workers=1)]
+    for c in cs:
+        assert 1000 <= c.num_vars <= 2000 and abs(c.num_clauses - 4.1 * c.num_vars) <= 1
+    p = learned.init_params(3)
+    assert p.shape == (tsat.MLP_NUM_PARAMS,) and p.dtype == np.float32
+    assert sum(int(np.prod(s)) for _, s in learned.SHAPES) == tsat.MLP_NUM_PARAMS
+
+
+def test_weights_roundtrip(tmp_path):
+    p = learned.init_params(4)
+    path = str(tmp_path / "w" / "m.npz")
+    learned.save_weights(path, p, {"a": 1})
+    q, meta = learned.load_weights(path)
+    assert np.array_equal(p, q) and meta == {"a": 1}
