@@ -796,7 +796,24 @@ __device__ __forceinline__ void cum_masks(const uint64_t (&w)[KO], uint64_t (&ge
 }
 
 template <int J, int KO, int G, int OP, bool FULL>
+__device__ __forceinline__ void var_pure_body(const VarArgs& a);
+
+// Uniform-width update kernel.  The batched gather needs its scalar
+// registers; the grouped one fits eight waves per SIMD.
+template <int J, int KO, int G, int OP, bool FULL>
 __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
+{
+    var_pure_body<J, KO, G, OP, FULL>(a);
+}
+
+template <int J, int KO, int G, int OP, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void var_pure8_kernel(VarArgs a)
+{
+    var_pure_body<J, KO, G, OP, FULL>(a);
+}
+
+template <int J, int KO, int G, int OP, bool FULL>
+__device__ __forceinline__ void var_pure_body(const VarArgs& a)
 {
     if (OP == OP_STEP && a.ctrl->stop) {
         copy_bits_on_stop(a);
@@ -810,7 +827,12 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
     const char* lit_base = (const char*)a.lits_cur;
     const uint32_t row_bytes = (uint32_t)W * 8u;
     constexpr int K1 = KO + 2; // R in 0..KO+1
-    float gt[K1][J];
+    // dL/dR table for the lane's candidates: in lane-private LDS slots for up
+    // to four candidate words (registers are kept for the prefetched row)
+    constexpr bool GT_LDS = J <= 4;
+    __shared__ float s_gt[4][GT_LDS ? K1 * J * 64 : 1];
+    float gt[GT_LDS ? 1 : K1][J];
+    float* my_gt = s_gt[threadIdx.x / 64u];
     uint32_t gt_inst = 0xffffffffu;
     int bad = 0;
     // G = 4 selects the batched scalar-memory gather (rows of up to four words)
@@ -832,7 +854,28 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
         b_inst = a.var_inst ? sload(a.var_inst + wave0) : 0u;
     }
 
+    // theta, m, v of the wave's next variable, loaded one variable ahead so
+    // that their latency hides behind the current variable's gather
+    constexpr bool PREFETCH = false;
+    float th_n[J], mm_n[J], vv_n[J];
+    bool valid_n[J];
+    if (PREFETCH && wave0 < (uint32_t)a.V) load_row<J, OP, FULL>(a, wave0, lane, th_n, mm_n, vv_n, valid_n);
+
     for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        float th[J], mm[J], vv[J];
+        bool valid[J];
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                th[j] = th_n[j];
+                mm[j] = mm_n[j];
+                vv[j] = vv_n[j];
+                valid[j] = valid_n[j];
+            }
+            if (v + nwaves < (uint32_t)a.V) load_row<J, OP, FULL>(a, v + nwaves, lane, th_n, mm_n, vv_n, valid_n);
+        } else {
+            load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
+        }
         VarInst vi;
         if constexpr (BATCHED) {
             if (a.var_inst && b_inst != vic.inst) vic = instance_state<OP>(a, b_inst);
@@ -858,11 +901,12 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
 #pragma unroll
             for (int r = 0; r < K1; ++r)
 #pragma unroll
-                for (int j = 0; j < J; ++j) gt[r][j] = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
+                for (int j = 0; j < J; ++j) {
+                    const float x = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
+                    if constexpr (GT_LDS) my_gt[(r * J + j) * 64 + lane] = x;
+                    else gt[r][j] = x;
+                }
         }
-        float th[J], mm[J], vv[J];
-        bool valid[J];
-        load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
         bool clamped = false;
         const bool need_mu = !(OP == OP_ADJ || a.mode != 1);
         double mu = 1.0;
@@ -1002,8 +1046,10 @@ __global__ __launch_bounds__(256) void var_pure_kernel(VarArgs a)
                 const uint32_t cn_lo = (O == 0) ? dn : cnt[1][O - 1][j];
                 const float np = (float)(cp_lo - cp_hi), nn = (float)(cn_lo - cn_hi);
                 // positive occurrence: R = x + O; negative: R = (1 - x) + O
-                const float gp = x ? gt[O + 1][j] : gt[O][j];
-                const float gn = x ? gt[O][j] : gt[O + 1][j];
+                const float g_lo = GT_LDS ? my_gt[(O * J + j) * 64 + lane] : gt[GT_LDS ? 0 : O][j];
+                const float g_hi = GT_LDS ? my_gt[((O + 1) * J + j) * 64 + lane] : gt[GT_LDS ? 0 : O + 1][j];
+                const float gp = x ? g_hi : g_lo;
+                const float gn = x ? g_lo : g_hi;
                 u = fmaf(np, gp, u);
                 u = fmaf(-nn, gn, u);
             }
@@ -1348,13 +1394,21 @@ static int occupancy_of(K kernel, size_t lds)
     return n;
 }
 
+// the batched gather keeps its scalar registers; the others run eight waves per SIMD
+template <int J, int KO, int G, int OP, bool FULL>
+static auto pure_kernel_ptr()
+{
+    if constexpr (G == 4 && J <= 4) return &var_pure_kernel<J, KO, G, OP, FULL>;
+    else return &var_pure8_kernel<J, KO, G, OP, FULL>;
+}
+
 template <int J, int KO, int G, bool FULL>
 static hipError_t launch_pure_jkgf(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
     switch (op) {
-    case OP_STEP: hipLaunchKernelGGL((var_pure_kernel<J, KO, G, OP_STEP, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
-    case OP_GRAD: hipLaunchKernelGGL((var_pure_kernel<J, KO, G, OP_GRAD, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((var_pure_kernel<J, KO, G, OP_ADJ, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_STEP: hipLaunchKernelGGL((pure_kernel_ptr<J, KO, G, OP_STEP, FULL>()), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_GRAD: hipLaunchKernelGGL((pure_kernel_ptr<J, KO, G, OP_GRAD, FULL>()), dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((pure_kernel_ptr<J, KO, G, OP_ADJ, FULL>()), dim3(blocks), dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
 }
@@ -1411,9 +1465,9 @@ template <int J, int KO>
 static int occupancy_pure(const VarArgs& a)
 {
     switch (pure_group(a, J)) {
-    case 4: return occupancy_of(var_pure_kernel<J, KO, (J <= 4 ? 4 : 1), OP_STEP, true>, 0);
-    case 2: return occupancy_of(var_pure_kernel<J, KO, (J <= 8 ? 2 : 1), OP_STEP, true>, 0);
-    default: return occupancy_of(var_pure_kernel<J, KO, 1, OP_STEP, true>, 0);
+    case 4: return occupancy_of(pure_kernel_ptr<J, KO, (J <= 4 ? 4 : 1), OP_STEP, true>(), 0);
+    case 2: return occupancy_of(pure_kernel_ptr<J, KO, (J <= 8 ? 2 : 1), OP_STEP, true>(), 0);
+    default: return occupancy_of(pure_kernel_ptr<J, KO, 1, OP_STEP, true>(), 0);
     }
 }
 
