@@ -11,7 +11,7 @@ resident in HBM before the timed region.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 10]
                        [--workload large|structured|tiny] [--no-cpu-baseline]
-                       [--calib-copy-mib M]
+                       [--no-learned] [--calib-copy-mib M]
 """
 from __future__ import annotations
 
@@ -93,6 +93,22 @@ def measured_traffic(workload):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def learned_vs_random():
+    """Steps / time to all-SAT (and to the 99% hand-off) from the trained
+    proposal network's start and from the N(0,1) start, on a held-out planted
+    3-SAT instance V = 100,000, C = 410,000, 128 restarts, same seeds."""
+    from paper_2511_07737_amd import learned
+
+    if not os.path.exists(learned.DEFAULT_WEIGHTS):
+        return None
+    print("[bench] learned vs random start", file=sys.stderr, flush=True)
+    weights, meta = learned.load_weights()
+    res = learned.compare(weights, V=100_000, restarts=128, max_steps=3600, seeds=(1, 2, 3))
+    res.pop("runs", None)
+    res["training"] = {k: meta.get(k) for k in ("instances", "rows", "val_accuracy", "final_loss", "epochs")}
+    return res
+
+
 def cpu_baseline(cnf, w, n_sample):
     """The FP64 oracle step, single-threaded, on the same instance with
     n_sample of the candidates."""
@@ -120,6 +136,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-versus-random start comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, launch one plain device copy kernel of this many MiB (read + write), "
                          "the reference point for scaling hardware byte counters")
@@ -188,6 +206,8 @@ def main():
         "best_sat_count": rep.best_sat_count,
         "first_sat_step": rep.first_sat_step,
     }
+    if not args.no_learned:
+        out["learned_vs_random"] = learned_vs_random()
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib << 20
         ms = s.copy_calibrate(nb)  # one copy kernel: nb bytes read, nb bytes written

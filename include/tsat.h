@@ -102,9 +102,10 @@ typedef struct {
     double loss;                  /* Eq. 3 of this instance at the last forward pass */
     uint64_t start_ticks;         /* device real-time counter at the first forward pass */
     uint64_t sat_ticks;           /* device real-time counter when first satisfied (0 if never) */
+    uint64_t conv_ticks;          /* device real-time counter when first converged (0 if never) */
     int32_t best_candidate;
     int32_t sat_candidate;        /* -1 if none */
-    int32_t frozen;               /* 1: stopped on its satisfying candidate (stop_on_sat) */
+    int32_t frozen;               /* 1: frozen by the stop mode of tsat_step */
     int32_t num_vars;
 } tsat_instance_status;
 
@@ -200,9 +201,13 @@ int32_t tsat_init_batch(tsat_solver* s, int32_t N, uint64_t seed, const float* i
 /* Run up to max_steps iterations (Sec. III-B, IV-A), each: forward R = P A
  * on the current bits -> SmoothMin/loss -> straight-through adjoint ->
  * Eq. 5 backward -> AdamW with lr(t) -> re-binarize.  Iteration t whose
- * forward finds a satisfying candidate is recorded in first_sat_step; with
- * stop_on_sat != 0 that instance is frozen there without updating (its
- * bits hold the witness) and the run stops once every instance is frozen.
+ * forward finds a satisfying candidate is recorded in first_sat_step, the
+ * first whose best candidate satisfies more than converge_frac*C clauses in
+ * first_converged_step.  stop_on_sat: 0 runs all max_steps; 1 freezes an
+ * instance without updating at its first satisfying candidate (its bits
+ * hold the witness); 2 freezes it at the first of that and convergence (the
+ * hand-off to CDCL of Sec. IV-B; its bits are the converged candidates);
+ * with 1 or 2 the run stops once every instance is frozen.
  * params NULL: the solver's defaults.  Blocks until the work is done and
  * fills *report (may be NULL); for a batch, loss and best_sat_count are
  * summed over the instances, first_sat_step is the earliest one, the
@@ -224,8 +229,8 @@ int32_t tsat_set_graph(tsat_solver* s, int32_t enable);
 /* Per-instance results for instances [first, first + count). */
 int32_t tsat_get_instance_status(tsat_solver* s, int32_t first, int32_t count, tsat_instance_status* out);
 
-/* Frequency in Hz of the device real-time counter behind start_ticks and
- * sat_ticks. */
+/* Frequency in Hz of the device real-time counter behind start_ticks,
+ * sat_ticks and conv_ticks. */
 int32_t tsat_device_clock_hz(tsat_solver* s, double* hz);
 
 /* Exact check of the current binarized batch (Sec. III-A, Satisfiability

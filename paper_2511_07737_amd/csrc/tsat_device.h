@@ -37,6 +37,7 @@ struct InstCtrl {
     int64_t best_sat;        // satisfied clauses of the best candidate, last forward
     uint64_t start_time;     // device real-time counter at the first forward
     uint64_t sat_time;       // device real-time counter when first satisfied
+    uint64_t conv_time;      // device real-time counter when first converged
     double loss;             // Eq. 3 at the last forward
     int32_t best_cand;
     int32_t sat_cand;        // first satisfying candidate
@@ -136,6 +137,8 @@ hipError_t launch_pack(const float* assign, int V, int N, int W, uint64_t* out, 
 hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, int blocks, hipStream_t st);
+hipError_t launch_strided_rows(const uint64_t* src, int64_t rows, int w, int64_t src_stride, uint64_t* dst,
+                               hipStream_t st);
 hipError_t launch_rank(const int64_t* sat, int N, int32_t* order, hipStream_t st);
 hipError_t launch_select(const SelectArgs& a, int nblocks, hipStream_t st);
 

@@ -991,7 +991,7 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
     HIPCHK(hipStreamSynchronize(s->stream));
     const int64_t updates0 = host.updates;
     host.stop = 0;
-    host.stop_on_sat = stop_on_sat ? 1 : 0;
+    host.stop_on_sat = stop_on_sat == 2 ? 2 : (stop_on_sat ? 1 : 0);
     HIPCHK(hipMemcpyAsync(ctrl, &host, sizeof host, hipMemcpyHostToDevice, s->stream));
 
     SminArgs sa = smin_args(s, p, s->N, s->Np);
@@ -1141,6 +1141,7 @@ int32_t tsat_get_instance_status(tsat_solver* s, int32_t first, int32_t count, t
         o.loss = x.loss;
         o.start_ticks = x.start_time;
         o.sat_ticks = x.sat_time;
+        o.conv_ticks = x.conv_time;
         o.best_candidate = x.best_cand;
         o.sat_candidate = x.sat_cand;
         o.frozen = x.frozen;
@@ -1233,9 +1234,13 @@ int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed)
     g_err.clear();
     RET(need_batch(s));
     if (!packed) return fail(TSAT_E_ARG, "packed is NULL");
-    // even literal rows hold the variable values
-    HIPCHK(hipMemcpy2DAsync(packed, (size_t)s->W * 8, s->lits[s->cur].p, (size_t)2 * s->W * 8, (size_t)s->W * 8, s->st.V,
-                            hipMemcpyDeviceToHost, s->stream));
+    // even literal rows hold the variable values: pack them on the device,
+    // then one contiguous copy
+    const size_t n = (size_t)s->st.V * s->W;
+    RET(s->tmp.reserve(n * 8, "bit staging"));
+    HIPCHK(launch_strided_rows(s->lits[s->cur].as<uint64_t>(), s->st.V, s->W, (int64_t)2 * s->W, s->tmp.as<uint64_t>(),
+                               s->stream));
+    HIPCHK(hipMemcpyAsync(packed, s->tmp.p, n * 8, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return TSAT_OK;
 }
@@ -1245,8 +1250,10 @@ static int32_t column_values(tsat_solver* s, int32_t cand, uint32_t v0, uint32_t
     const size_t n = v1 - v0;
     std::vector<uint64_t> col(n);
     if (n) {
-        HIPCHK(hipMemcpy2DAsync(col.data(), 8, s->lits[s->cur].as<uint64_t>() + (size_t)2 * v0 * s->W + (cand >> 6),
-                                (size_t)2 * s->W * 8, 8, n, hipMemcpyDeviceToHost, s->stream));
+        RET(s->tmp.reserve(n * 8, "bit staging"));
+        HIPCHK(launch_strided_rows(s->lits[s->cur].as<uint64_t>() + (size_t)2 * v0 * s->W + (cand >> 6), (int64_t)n, 1,
+                                   (int64_t)2 * s->W, s->tmp.as<uint64_t>(), s->stream));
+        HIPCHK(hipMemcpyAsync(col.data(), s->tmp.p, n * 8, hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
     for (size_t v = 0; v < n; ++v) vals[v] = (uint8_t)((col[v] >> (cand & 63)) & 1u);

@@ -348,9 +348,15 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
             ic->sat_time = now;
             ic->witness_pending = 1;
         }
-        if ((double)s_best[0] > a.conv_frac * (double)info.C && ic->first_conv_step < 0) ic->first_conv_step = t;
-        if (a.update && ctrl && any_sat && ctrl->stop_on_sat) {
-            // freeze: the current bits keep the witness, no more updates
+        const bool converged = (double)s_best[0] > a.conv_frac * (double)info.C;
+        if (converged && ic->first_conv_step < 0) {
+            ic->first_conv_step = t;
+            ic->conv_time = now;
+        }
+        // stop mode 1: freeze on a satisfying candidate; 2: also on
+        // convergence, the hand-off point of Sec. IV-B
+        if (a.update && ctrl && ctrl->stop_on_sat && (any_sat || (ctrl->stop_on_sat == 2 && converged))) {
+            // freeze: the current bits stay (a witness if satisfied), no more updates
             ic->frozen = 1;
             ic->witness_pending = 0;
             const int nf = atomicAdd(&ctrl->n_frozen, 1) + 1;
@@ -1193,6 +1199,17 @@ __global__ void copy16_kernel(uint4* __restrict__ dst, const uint4* __restrict__
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) dst[e] = src[e];
 }
 
+// dst[r][j] = src[r * src_stride + j] for r < rows, j < w (64-bit words):
+// strided rows packed for one contiguous device-to-host copy
+__global__ void strided_rows_kernel(const uint64_t* __restrict__ src, int64_t rows, int w, int64_t src_stride,
+                                    uint64_t* __restrict__ dst)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * w) return;
+    const int64_t r = e / w;
+    dst[e] = src[r * src_stride + (e - r * w)];
+}
+
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t val)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1517,6 +1534,16 @@ hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(init_normal_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_rows(const uint64_t* src, int64_t rows, int w, int64_t src_stride, uint64_t* dst,
+                               hipStream_t st)
+{
+    const int64_t n = rows * w;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(strided_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, rows, w,
+                       src_stride, dst);
     return hipGetLastError();
 }
 

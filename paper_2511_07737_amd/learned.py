@@ -86,7 +86,7 @@ def label_chunk(cnfs, restarts: int, max_steps: int, params, seed: int, rows_per
     s.load_batch(cnfs)
     s.init_batch(restarts, seed=seed)
     s.set_graph(True)
-    s.step(max_steps, stop_on_sat=True)
+    s.step(max_steps, stop_on_sat=2)  # every instance stops at its hand-off point
     st = s.instance_status()
     bits = s.get_bits()
     X = s.get_features()

@@ -62,24 +62,74 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
+def log(msg: str) -> None:
+    print(f"[ragged] {msg}", file=sys.stderr, flush=True)
+
+
+def run_steps(s, max_steps: int, stop_mode: int, chunk: int = 200):
+    """tsat_step in chunks (the stop state carries over between calls),
+    reporting progress; returns the total steps done and the last report."""
+    done, rep = 0, None
+    while done < max_steps:
+        rep = s.step(min(chunk, max_steps - done), stop_on_sat=stop_mode)
+        done += rep.steps_done
+        st = s.instance_status()
+        frozen = sum(x["frozen"] for x in st)
+        log(f"step {done}: {frozen}/{len(st)} instances frozen")
+        if frozen == len(st) or rep.steps_done == 0:
+            break
+    return done, rep
+
+
 def solve_batch(cnfs, restarts: int, max_steps: int, params, seed: int = 1, autotune_iters: int = 2,
                 graph: bool = True, verify: bool = True, device: int = 0) -> dict:
     s = tsat.Solver(device=device, params=params)
     t0 = time.perf_counter()
     s.load_batch(cnfs)
     t_load = time.perf_counter() - t0
+    log(f"loaded in {t_load:.1f} s")
     tune = None
     if autotune_iters > 0:
         s.init_batch(restarts, seed=seed)
         c, used = s.autotune(autotune_iters)
         tune = dict(c.as_dict(), iterations=used)
+        log(f"autotuned: {tune}")
+    hz = s.device_clock_hz()
+    n = len(cnfs)
+    out = {
+        "instances": n,
+        "restarts": restarts,
+        "total_vars": int(sum(c.num_vars for c in cnfs)),
+        "total_clauses": int(sum(c.num_clauses for c in cnfs)),
+        "total_lits": int(sum(c.num_lits for c in cnfs)),
+        "load_s": t_load,
+        "launch_config": tune,
+    }
+    # phase 1: until every instance hands off (converged or satisfied)
     s.init_batch(restarts, seed=seed)  # the timed solve starts fresh
     s.set_graph(graph)
     t0 = time.perf_counter()
-    rep = s.step(max_steps, stop_on_sat=True)
+    steps1, rep = run_steps(s, max_steps, 2)
     wall = time.perf_counter() - t0
     st = s.instance_status()
-    hz = s.device_clock_hz()
+    done = [j for j, x in enumerate(st) if x["frozen"]]
+    tth = [((x["sat_ticks"] if x["first_sat_step"] >= 0 and (x["first_converged_step"] < 0 or
+             x["first_sat_step"] <= x["first_converged_step"]) else x["conv_ticks"]) - x["start_ticks"]) / hz
+           for x in (st[j] for j in done)]
+    out["handoff"] = {
+        "handed_off": len(done), "frac": len(done) / n, "steps_done": steps1, "wall_s": wall,
+        "ms_per_step": 1e3 * wall / max(1, steps1),
+        "instances_per_s": len(done) / wall if wall > 0 else None,
+        "p50_time_s": percentile(tth, 50), "p99_time_s": percentile(tth, 99),
+        "p50_steps": percentile([min(x for x in (st[j]["first_sat_step"], st[j]["first_converged_step"]) if x >= 0)
+                                 for j in done], 50),
+    }
+    # phase 2: from the same start until every instance is satisfied or the cap
+    s.init_batch(restarts, seed=seed)
+    t0 = time.perf_counter()
+    steps2, rep = run_steps(s, max_steps, 1)
+    wall = time.perf_counter() - t0
+    st = s.instance_status()
     solved = [j for j, x in enumerate(st) if x["first_sat_step"] >= 0]
     tts = [(st[j]["sat_ticks"] - st[j]["start_ticks"]) / hz for j in solved]
     steps = [st[j]["first_sat_step"] for j in solved]
@@ -91,28 +141,21 @@ def solve_batch(cnfs, restarts: int, max_steps: int, params, seed: int = 1, auto
                 bad.append(j)
     conv = [j for j, x in enumerate(st) if x["first_converged_step"] >= 0]
     s.close()
-    n = len(cnfs)
-    return {
-        "instances": n,
-        "restarts": restarts,
-        "total_vars": int(sum(c.num_vars for c in cnfs)),
-        "total_clauses": int(sum(c.num_clauses for c in cnfs)),
-        "total_lits": int(sum(c.num_lits for c in cnfs)),
+    out.update({
         "solved": len(solved),
         "solved_frac": len(solved) / n,
         "converged_frac": len(conv) / n,
         "witnesses_failing_host_check": len(bad),
-        "steps_done": rep.steps_done,
+        "steps_done": steps2,
         "wall_s": wall,
-        "ms_per_step": 1e3 * wall / max(1, rep.steps_done),
+        "ms_per_step": 1e3 * wall / max(1, steps2),
         "instances_per_s": len(solved) / wall if wall > 0 else None,
         "p50_time_to_sat_s": percentile(tts, 50),
         "p99_time_to_sat_s": percentile(tts, 99),
         "p50_steps_to_sat": percentile(steps, 50),
         "p99_steps_to_sat": percentile(steps, 99),
-        "load_s": t_load,
-        "launch_config": tune,
-    }
+    })
+    return out
 
 
 def main(argv=None):

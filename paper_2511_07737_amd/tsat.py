@@ -65,6 +65,7 @@ class _InstStatus(ct.Structure):
     _fields_ = [
         ("first_sat_step", _i64), ("first_converged_step", _i64), ("best_sat_count", _i64),
         ("num_clauses", _i64), ("loss", _f64), ("start_ticks", _u64), ("sat_ticks", _u64),
+        ("conv_ticks", _u64),
         ("best_candidate", _i32), ("sat_candidate", _i32), ("frozen", _i32), ("num_vars", _i32),
     ]
 
@@ -367,11 +368,14 @@ class Solver:
         self.N = int(n)
 
     # solving ------------------------------------------------------------
-    def step(self, max_steps: int = 1, params: Params | None = None, stop_on_sat: bool = False,
+    def step(self, max_steps: int = 1, params: Params | None = None, stop_on_sat: bool | int = False,
              raise_numeric: bool = True) -> Report:
+        """stop_on_sat: False/0 run all steps; True/1 freeze instances on a
+        satisfying candidate; 2 also freeze them at convergence (hand-off)."""
         r = _Report()
+        mode = 2 if stop_on_sat == 2 else (1 if stop_on_sat else 0)
         rc = lib().tsat_step(self._h, int(max_steps), ct.byref(params) if params is not None else None,
-                             1 if stop_on_sat else 0, ct.byref(r))
+                             mode, ct.byref(r))
         if rc != OK and not (rc == E_NUMERIC and not raise_numeric):
             _check(rc)
         return Report(*[getattr(r, f) for f, _ in _Report._fields_ if f != "reserved"])

@@ -145,3 +145,25 @@ def test_freeze_on_sat_per_instance(solver):
         assert np.array_equal(th_a[base[j]:base[j + 1]], th_b[base[j]:base[j + 1]])
     assert not np.array_equal(th_a[base[-2]:base[-1]], th_b[base[-2]:base[-1]])
     assert solver.device_clock_hz() > 0
+
+
+def test_handoff_stop_mode_freezes_at_convergence(solver):
+    """Stop mode 2 freezes each instance at its first converged (or
+    satisfied) iteration, the hand-off point; frozen bits stay put."""
+    cnfs = [gen.planted_ksat(300 + 40 * j, int(4.1 * (300 + 40 * j)), 3, seed=70 + j) for j in range(6)]
+    solver.load_batch(cnfs)
+    p = tsat.default_params(norm_mode=tsat.MODE_NONE, tau=2.0)
+    solver.init_batch(64, seed=3)
+    r = solver.step(2000, params=p, stop_on_sat=2)
+    st = solver.instance_status()
+    assert r.steps_done < 2000
+    for x in st:
+        assert x["frozen"] == 1
+        first = [s for s in (x["first_sat_step"], x["first_converged_step"]) if s >= 0]
+        assert first
+        if x["first_converged_step"] >= 0:
+            assert x["conv_ticks"] >= x["start_ticks"] > 0
+            assert x["best_sat_count"] > 0.99 * x["num_clauses"]
+    bits = solver.get_bits()
+    solver.step(5, params=p, stop_on_sat=2)
+    assert np.array_equal(solver.get_bits(), bits)
