@@ -434,7 +434,9 @@ typedef struct {
                                   follows from it); default 1024 */
     int32_t var_blocks_per_cu; /* fused update: persistent blocks per CU, 0 = 4 x occupancy */
     int32_t pure_group;        /* uniform-width stores: occurrence records per load group, 1, 2 or 4 */
-    int32_t reserved;
+    int32_t clause_planes;     /* uniform widths 2, 3 and N <= 256: 1 = the forward stores R of every
+                                  clause in binary and the update gathers it (one record per
+                                  occurrence), 0 = the update gathers the other literals' rows */
     double fwd_ms;             /* tsat_autotune output: forward time per iteration of the choice */
     double var_ms;             /* tsat_autotune output: fused update time per iteration of the choice */
 } tsat_launch_config;
@@ -444,15 +446,16 @@ int32_t tsat_get_launch_config(tsat_solver* s, tsat_launch_config* out);
 
 /* Set launch shapes (fwd_ms/var_ms ignored); drops a captured graph.
  * E_ARG outside the documented ranges.  The environment variables
- * TSAT_FWD_TARGET_BLOCKS, TSAT_VAR_BLOCKS_PER_CU and TSAT_PURE_GROUP set the
- * initial values of a new solver. */
+ * TSAT_FWD_TARGET_BLOCKS, TSAT_VAR_BLOCKS_PER_CU, TSAT_PURE_GROUP and
+ * TSAT_CLAUSE_PLANES set the initial values of a new solver. */
 int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg);
 
 /* Autotuner: times candidate shapes on real iterations of the current batch
  * (`iters` in [1, 64] iterations per candidate, per-kernel HIP-event timing):
  * first the forward work-unit target (256..4096), then the fused update's
  * blocks per CU (auto, 8, 16, 32, 64) with, for uniform-width stores, the
- * record group (1, 2, 4); keeps the fastest of each and returns it in *best
+ * clause-plane gather on and off and, without it, the record group (1, 2,
+ * 4), compared on forward + update time; keeps the fastest and returns it in *best
  * (may be NULL) with the measured times.  The iterations advance the batch
  * (p as in tsat_step, no early stop); *iters_used (may be NULL) receives
  * their number.  Callers that want a fresh start re-initialize the batch. */

@@ -72,6 +72,8 @@ struct FwdArgs {
     int64_t H_stride;       // Np * K1
     const Ctrl* ctrl;       // may be null
     const InstCtrl* ictrl;  // may be null
+    uint32_t* planes;       // null, or [Cb][2][plane_stride]: bits 0 and 1 of R per clause (widths 2, 3)
+    int32_t plane_stride;   // dwords per plane row (2 J, J the update kernel's words per candidate row)
 };
 
 struct SminArgs {
@@ -116,6 +118,11 @@ struct VarArgs {
     Ctrl* ctrl;
     const InstCtrl* ictrl;    // may be null
     uint8_t* witness;         // [V]
+    // clause-plane gather (uniform widths 2 and 3): per variable, positive
+    // then negative records holding the clause index (offsets as occ_off /
+    // occ_mid), and the forward pass's planes of R for these bits
+    const uint32_t* occ_cid;  // null: gather the other literals' rows instead
+    const uint32_t* planes;   // [Cb][2][2 J] dwords
 };
 
 struct SelectArgs {

@@ -49,6 +49,8 @@ struct Store {
     // pure_k in 2..4): record offsets of header-less records of k-1 codes.
     int32_t pure_k = 0;
     std::vector<uint32_t> occ_off, occ_mid, occ_data;
+    // uniform widths 2 and 3: the same records as clause indices within the bucket
+    std::vector<uint32_t> occ_cid;
 };
 
 static inline uint32_t lit_code(int32_t x, uint32_t base)
@@ -163,6 +165,8 @@ static int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_
         const uint64_t words = pure ? total * (uint64_t)(st.pure_k - 1) : total;
         if (words > 0xffffffffull) return fail(TSAT_E_ARG, "occurrence store exceeds 2^32 words");
         st.occ_data.assign(words, 0);
+        const bool cid = pure && (st.pure_k == 2 || st.pure_k == 3);
+        if (cid) st.occ_cid.assign(total, 0);
         std::vector<uint32_t> curp(V), curn(V);
         for (int32_t v = 0; v < V; ++v) {
             curp[v] = st.occ_off[v];
@@ -180,6 +184,7 @@ static int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_
                         size_t w = (size_t)pos * (size_t)(k - 1);
                         for (int f = 0; f < k; ++f)
                             if (f != e) st.occ_data[w++] = lit[f];
+                        if (cid) st.occ_cid[pos] = (uint32_t)c;
                         ++pos;
                     } else {
                         st.occ_data[pos++] = (uint32_t)(k - 1);
@@ -222,6 +227,8 @@ struct tsat_solver {
     Store st;
     std::vector<Bucket*> buckets;
     DBuf occ_off, occ_mid, occ_data, var_inst, info;
+    DBuf occ_cid;            // clause-index records (uniform widths 2, 3)
+    DBuf planes, planes_scr; // R of every clause in binary, for the step / for evaluations
 
     // batch
     int32_t N = 0, W = 0, Np = 0;
@@ -245,6 +252,7 @@ struct tsat_solver {
     int32_t fwd_target_blocks = 1024; // forward work units per launch to aim for
     int32_t var_per_cu = 0;           // variable-major blocks per CU (0: 4 x occupancy)
     int32_t pure_group = 2;           // records per load group, uniform-width stores
+    int32_t clause_planes = 1;        // uniform widths 2, 3: backward gathers the forward's planes of R
 
     // learned proposal: features and aggregation channels, kept proposal
     DBuf feat, fh[2], fzinv, prop;
@@ -354,8 +362,28 @@ static int32_t prepare_units(tsat_solver* s, int32_t N)
 }
 
 // enqueue the forward histograms of every width bucket on literal rows `lits`
+// Words per candidate row the update kernels use for W words (a power of two).
+static int32_t row_words(int32_t W) { return W <= 2 ? W : (W <= 4 ? 4 : (W <= 8 ? 8 : 16)); }
+
+// The clause-plane update applies: uniform widths 2 or 3, at most 256 candidates.
+static bool plane_path(const tsat_solver* s, int32_t N)
+{
+    return s->clause_planes && s->occ_cid.p && (N + 63) / 64 <= 4;
+}
+
+// Planes of R for N candidates: [Cb][2][2 J] dwords, zeroed when (re)allocated.
+static int32_t ensure_planes(tsat_solver* s, DBuf& buf, int32_t N, hipStream_t st)
+{
+    const size_t Cb = (size_t)s->st.width_count[s->st.pure_k];
+    const size_t bytes = std::max<size_t>(16, Cb * 16 * (size_t)row_words((N + 63) / 64));
+    if (buf.p && buf.bytes >= bytes) return TSAT_OK;
+    RET(buf.alloc(bytes, "clause planes"));
+    HIPCHK(launch_fill_u32(buf.as<uint32_t>(), (int64_t)(bytes / 4), 0u, st));
+    return TSAT_OK;
+}
+
 static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint32_t* H, const Ctrl* ctrl,
-                           const InstCtrl* ictrl, hipStream_t st)
+                           const InstCtrl* ictrl, hipStream_t st, uint32_t* planes = nullptr)
 {
     const int32_t W = (N + 63) / 64;
     for (auto* b : s->buckets) {
@@ -377,6 +405,10 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
         a.H_stride = (int64_t)64 * W * a.K1;
         a.ctrl = ctrl;
         a.ictrl = ictrl;
+        if (planes && plane_path(s, N) && b->k == s->st.pure_k) {
+            a.planes = planes;
+            a.plane_stride = 2 * row_words(W);
+        }
         HIPCHK(launch_fwd(a, nunits, g.tiles, st));
     }
     return TSAT_OK;
@@ -434,6 +466,10 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.one_minus_beta1 = (float)(1.0 - p.beta1);
     a.one_minus_beta2 = (float)(1.0 - p.beta2);
     a.eps = (float)p.eps;
+    // clause-plane gather: evaluations write their planes to planes_scr, the
+    // step overrides this with its own buffer
+    a.occ_cid = plane_path(s, N) ? s->occ_cid.as<uint32_t>() : nullptr;
+    a.planes = s->planes_scr.as<uint32_t>();
     return a;
 }
 
@@ -658,6 +694,7 @@ int32_t tsat_create(const tsat_config* cfg, tsat_solver** out)
     s->fwd_target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", s->fwd_target_blocks));
     s->var_per_cu = std::max(0, env_int("TSAT_VAR_BLOCKS_PER_CU", s->var_per_cu));
     s->pure_group = env_int("TSAT_PURE_GROUP", s->pure_group);
+    s->clause_planes = env_int("TSAT_CLAUSE_PLANES", s->clause_planes) != 0;
     if (cfg && cfg->stream) {
         s->stream = (hipStream_t)cfg->stream;
     } else {
@@ -722,6 +759,15 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     RET(s->occ_data.alloc((occ_words + 64) * 4, "occurrence records"));
     HIPCHK(launch_fill_u32(s->occ_data.as<uint32_t>() + occ_words, 64, 0u, s->stream));
     if (occ_words) HIPCHK(hipMemcpy(s->occ_data.p, s->st.occ_data.data(), occ_words * 4, hipMemcpyHostToDevice));
+    s->occ_cid.release();
+    if (!s->st.occ_cid.empty()) {
+        const size_t nr = s->st.occ_cid.size();
+        RET(s->occ_cid.alloc((nr + 64) * 4, "clause-index records"));
+        HIPCHK(launch_fill_u32(s->occ_cid.as<uint32_t>() + nr, 64, 0u, s->stream));
+        HIPCHK(hipMemcpy(s->occ_cid.p, s->st.occ_cid.data(), nr * 4, hipMemcpyHostToDevice));
+    }
+    s->planes.release();
+    s->planes_scr.release();
     const size_t ni = (size_t)s->st.n_inst;
     RET(s->info.alloc(ni * sizeof(InstInfo), "instance sizes"));
     HIPCHK(hipMemcpy(s->info.p, s->st.info.data(), ni * sizeof(InstInfo), hipMemcpyHostToDevice));
@@ -812,6 +858,7 @@ static int32_t alloc_batch(tsat_solver* s, int32_t N)
     HIPCHK(launch_fill_u32(s->H_last.as<uint32_t>(), (int64_t)(ni * Np * K1), 0u, s->stream));
     HIPCHK(launch_fill_u32(s->m.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
     HIPCHK(launch_fill_u32(s->v.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
+    if (plane_path(s, N)) RET(ensure_planes(s, s->planes, N, s->stream));
     s->N = N;
     s->W = W;
     s->Np = Np;
@@ -963,7 +1010,8 @@ static int32_t enqueue_iteration(tsat_solver* s, const SminArgs& sa, VarArgs va,
 {
     Ctrl* ctrl = s->ctrl.as<Ctrl>();
     InstCtrl* ictrl = s->ictrl.as<InstCtrl>();
-    RET(enqueue_fwd(s, s->lits[cur].as<uint64_t>(), s->N, s->H.as<uint32_t>(), ctrl, ictrl, s->stream));
+    RET(enqueue_fwd(s, s->lits[cur].as<uint64_t>(), s->N, s->H.as<uint32_t>(), ctrl, ictrl, s->stream,
+                    plane_path(s, s->N) ? s->planes.as<uint32_t>() : nullptr));
     if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 1], s->stream));
     HIPCHK(launch_smin(sa, s->stream));
     if (timing) HIPCHK(hipEventRecord(s->events[3 * it + 2], s->stream));
@@ -1004,6 +1052,7 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
     sa.ictrl = s->ictrl.as<InstCtrl>();
     sa.update = 1;
     VarArgs va = var_args(s, p, s->N, s->W, s->Np);
+    va.planes = s->planes.as<uint32_t>();
     va.tbl = s->table.as<float>();
     va.theta = s->theta.as<float>();
     va.m = s->m.as<float>();
@@ -1166,7 +1215,12 @@ static int32_t eval_rows(tsat_solver* s, const tsat_params& p, const uint64_t* l
                          uint32_t* H_out, float* S32, double* S64, int64_t* sat, float* table, hipStream_t st)
 {
     const int32_t W = (N + 63) / 64, Np = 64 * W;
-    RET(enqueue_fwd(s, lits, N, s->H_scr.as<uint32_t>(), nullptr, nullptr, st));
+    uint32_t* planes = nullptr;
+    if (plane_path(s, N)) {
+        RET(ensure_planes(s, s->planes_scr, N, st));
+        planes = s->planes_scr.as<uint32_t>();
+    }
+    RET(enqueue_fwd(s, lits, N, s->H_scr.as<uint32_t>(), nullptr, nullptr, st, planes));
     SminArgs a = smin_args(s, p, N, Np);
     a.H = s->H_scr.as<uint32_t>();
     a.H_last = H_out;
@@ -1523,6 +1577,7 @@ static int32_t check_launch_config(const tsat_launch_config* c)
         return fail(TSAT_E_ARG, "var_blocks_per_cu must be in [0, 1024]");
     if (c->pure_group != 1 && c->pure_group != 2 && c->pure_group != 4)
         return fail(TSAT_E_ARG, "pure_group must be 1, 2 or 4");
+    if (c->clause_planes != 0 && c->clause_planes != 1) return fail(TSAT_E_ARG, "clause_planes must be 0 or 1");
     return TSAT_OK;
 }
 
@@ -1534,6 +1589,7 @@ int32_t tsat_get_launch_config(tsat_solver* s, tsat_launch_config* out)
     out->fwd_target_blocks = s->fwd_target_blocks;
     out->var_blocks_per_cu = s->var_per_cu;
     out->pure_group = s->pure_group;
+    out->clause_planes = s->clause_planes;
     return TSAT_OK;
 }
 
@@ -1548,6 +1604,8 @@ int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg)
     s->fwd_target_blocks = cfg->fwd_target_blocks;
     s->var_per_cu = cfg->var_blocks_per_cu;
     s->pure_group = cfg->pure_group;
+    s->clause_planes = cfg->clause_planes;
+    if (s->N > 0 && plane_path(s, s->N)) RET(ensure_planes(s, s->planes, s->N, s->stream));
     return TSAT_OK;
 }
 
@@ -1599,20 +1657,29 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
     // uniform-width stores
     static const int kPerCu[] = {0, 8, 16, 32, 64};
     const bool pure = s->st.pure_k != 0;
+    const bool planes_apply = s->occ_cid.p && (s->N + 63) / 64 <= 4;
     static const int kGroups[] = {1, 2, 4};
-    double best_var = 1e30;
+    double best_var = 1e30, best_sum = 1e30;
     tsat_launch_config pick = cur;
-    for (int pc : kPerCu) {
-        for (int gi = 0; gi < (pure ? 3 : 1); ++gi) {
-            tsat_launch_config c = cur;
-            c.var_blocks_per_cu = pc;
-            c.pure_group = pure ? kGroups[gi] : cur.pure_group;
-            RET(tsat_set_launch_config(s, &c));
-            RET(time_iterations(s, iters, p, ms));
-            used += iters;
-            if (ms[2] < best_var) {
-                best_var = ms[2];
-                pick = c;
+    // with clause planes the record group does not apply; the forward writes
+    // the planes, so the shapes are compared on forward + update time
+    for (int cp = planes_apply ? 1 : 0; cp >= 0; --cp) {
+        const int ngroups = (pure && !cp) ? 3 : 1;
+        for (int pc : kPerCu) {
+            for (int gi = 0; gi < ngroups; ++gi) {
+                tsat_launch_config c = cur;
+                c.var_blocks_per_cu = pc;
+                c.pure_group = ngroups > 1 ? kGroups[gi] : cur.pure_group;
+                c.clause_planes = planes_apply ? cp : cur.clause_planes;
+                RET(tsat_set_launch_config(s, &c));
+                RET(time_iterations(s, iters, p, ms));
+                used += iters;
+                if (ms[0] + ms[2] < best_sum) {
+                    best_sum = ms[0] + ms[2];
+                    best_var = ms[2];
+                    best_fwd = ms[0];
+                    pick = c;
+                }
             }
         }
     }

@@ -137,6 +137,16 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
                 for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x;
                 ge[0] |= x;
             }
+            if (KW >= 2 && KW <= 3 && a.planes) {
+                // R in binary for the backward: bit 0 = parity of the
+                // cumulative masks, bit 1 = [R >= 2] (R <= 3)
+                uint32_t b0 = 0;
+#pragma unroll
+                for (int r = 0; r < KW; ++r) b0 ^= ge[r];
+                uint32_t* P = a.planes + (size_t)c * (2 * a.plane_stride);
+                P[d] = b0;
+                P[a.plane_stride + d] = ge[KW >= 2 ? 1 : 0];
+            }
 #pragma unroll
             for (int r = 0; r < KW; ++r) {
                 uint32_t carry = ge[r];
@@ -1070,6 +1080,148 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
 }
 
 // ---------------------------------------------------------------------------
+// Uniform-width update with the clause-plane gather (widths 2 and 3).
+//
+// The forward pass leaves R of every clause in binary (two bit planes per
+// candidate row), so the adjoint of Sec. III-B needs no other literal rows:
+// U_vi = sum over the positive occurrences of dL/dR_i[R_ci] minus the same
+// over the negative ones.  Per record the wave gathers one clause's planes
+// (2 J words through the scalar cache) and counts, per candidate and sign,
+// the records with R >= r as carry-in masks of v_addc; U is formed from the
+// exact counts and the dL/dR table.  The rest is the tail shared with the
+// other update kernels.
+// ---------------------------------------------------------------------------
+template <int J, int KW, int OP, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void var_plane_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) {
+        copy_bits_on_stop(a);
+        return;
+    }
+    constexpr int G = 2;       // records per scalar-load group
+    constexpr int K1 = KW + 1; // R in 0..KW
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const int W = a.W, Np = a.Np;
+    const StepScalars c = load_scalars(a, OP);
+    const char* plane_base = (const char*)a.planes;
+    constexpr uint32_t plane_bytes = 16u * J; // two planes of J words
+    __shared__ float s_gt[4][K1 * J * 64];
+    float* my_gt = s_gt[threadIdx.x / 64u];
+    uint32_t gt_inst = 0xffffffffu;
+    int bad = 0;
+
+    for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        const VarInst vi = var_instance<OP>(a, v);
+        if (vi.frozen) {
+            keep_variable<J>(a, v, lane);
+            continue;
+        }
+        if (vi.inst != gt_inst) {
+            gt_inst = vi.inst;
+            const float* tg = a.tbl + (size_t)vi.inst * K1 * Np;
+#pragma unroll
+            for (int r = 0; r < K1; ++r)
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    my_gt[(r * J + j) * 64 + lane] = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
+        }
+        float th[J], mm[J], vv[J];
+        bool valid[J];
+        load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
+        bool clamped = false;
+        const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+        uint32_t cnt[2][KW][J];
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+            for (int r = 0; r < KW; ++r)
+#pragma unroll
+                for (int j = 0; j < J; ++j) cnt[sg][r][j] = 0;
+        const uint32_t r0 = sload(a.occ_off + v), rm = sload(a.occ_mid + v), r1 = sload(a.occ_off + v + 1);
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const uint32_t beg = sg ? rm : r0, end = sg ? r1 : rm;
+            // the clause indices of the next group come with the planes of
+            // the current one (the index array is padded past its end)
+            uint32_t id_next[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) id_next[g] = sload(a.occ_cid + beg + g);
+            for (uint32_t q = beg; q < end; q += G) {
+                uint32_t id[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) id[g] = id_next[g];
+                uint64_t w[G][2][J];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const uint64_t* pl = (const uint64_t*)(plane_base + id[g] * plane_bytes);
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int j = 0; j < J; ++j) w[g][p][j] = sload(pl + p * J + j);
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g) id_next[g] = sload(a.occ_cid + q + G + g);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bool live = q + g < end; // wave-uniform
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const uint64_t b0 = live ? w[g][0][j] : 0ull, b1 = live ? w[g][1][j] : 0ull;
+                        cnt[sg][0][j] = add_lane_bit(cnt[sg][0][j], b0 | b1); // R >= 1
+                        cnt[sg][1][j] = add_lane_bit(cnt[sg][1][j], b1);      // R >= 2
+                        if constexpr (KW == 3) cnt[sg][2][j] = add_lane_bit(cnt[sg][2][j], b0 & b1); // R = 3
+                    }
+                }
+            }
+        }
+        const uint32_t dp = rm - r0, dn = r1 - rm;
+        // U in the same order of operations as the row-gather kernels (so
+        // that the two gathers give identical results): per count O of the
+        // other true literals, the positive occurrences (R = x + O) and the
+        // negative ones (R = 1 - x + O), x the lane's own value
+        const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+        uint64_t oP[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+        double U[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t x = add_lane_bit(0u, oP[j]);
+            uint32_t gep[KW + 2], gen[KW + 2]; // records with R >= r, per sign
+            gep[0] = dp;
+            gen[0] = dn;
+#pragma unroll
+            for (int r = 1; r <= KW; ++r) {
+                gep[r] = cnt[0][r - 1][j];
+                gen[r] = cnt[1][r - 1][j];
+            }
+            gep[KW + 1] = 0u;
+            gen[KW + 1] = 0u;
+            float u = 0.f;
+#pragma unroll
+            for (int O = 0; O < KW; ++O) {
+                const float np = (float)(x ? gep[O + 1] - gep[O + 2] : gep[O] - gep[O + 1]);
+                const float nn = (float)(x ? gen[O] - gen[O + 1] : gen[O + 1] - gen[O + 2]);
+                const float g_lo = my_gt[(O * J + j) * 64 + lane];
+                const float g_hi = my_gt[((O + 1) * J + j) * 64 + lane];
+                const float gp = x ? g_hi : g_lo;
+                const float gn = x ? g_lo : g_hi;
+                u = fmaf(np, gp, u);
+                u = fmaf(-nn, gn, u);
+            }
+            U[j] = (double)u;
+        }
+        var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
+    }
+    if (OP == OP_STEP) {
+        if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
+        advance_step(a);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
 
@@ -1466,8 +1618,34 @@ static hipError_t launch_pure_j(const VarArgs& a, int op, int blocks, hipStream_
     }
 }
 
+template <int J, int KW, bool FULL>
+static hipError_t launch_plane_jkf(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    switch (op) {
+    case OP_STEP: hipLaunchKernelGGL((var_plane_kernel<J, KW, OP_STEP, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_GRAD: hipLaunchKernelGGL((var_plane_kernel<J, KW, OP_GRAD, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((var_plane_kernel<J, KW, OP_ADJ, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int J>
+static hipError_t launch_plane_j(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    const bool full = a.N == 64 * J;
+    if (a.pure_k == 2) return full ? launch_plane_jkf<J, 2, true>(a, op, blocks, st) : launch_plane_jkf<J, 2, false>(a, op, blocks, st);
+    return full ? launch_plane_jkf<J, 3, true>(a, op, blocks, st) : launch_plane_jkf<J, 3, false>(a, op, blocks, st);
+}
+
 hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
+    if (a.occ_cid && a.planes && op != OP_BINARIZE && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
+        switch (a.W) {
+        case 1: return launch_plane_j<1>(a, op, blocks, st);
+        case 2: return launch_plane_j<2>(a, op, blocks, st);
+        default: return launch_plane_j<4>(a, op, blocks, st);
+        }
+    }
     const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;
     switch (a.W) {
     case 1: return pure ? launch_pure_j<1>(a, op, blocks, st) : launch_var_j<1>(a, op, blocks, st);
@@ -1504,6 +1682,14 @@ static int occupancy_j(const VarArgs& a, bool pure)
 
 int var_occupancy(const VarArgs& a, int op)
 {
+    if (a.occ_cid && a.planes && op != OP_BINARIZE && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
+        const bool k2 = a.pure_k == 2;
+        switch (a.W) {
+        case 1: return k2 ? occupancy_of(var_plane_kernel<1, 2, OP_STEP, false>, 0) : occupancy_of(var_plane_kernel<1, 3, OP_STEP, false>, 0);
+        case 2: return k2 ? occupancy_of(var_plane_kernel<2, 2, OP_STEP, false>, 0) : occupancy_of(var_plane_kernel<2, 3, OP_STEP, false>, 0);
+        default: return k2 ? occupancy_of(var_plane_kernel<4, 2, OP_STEP, false>, 0) : occupancy_of(var_plane_kernel<4, 3, OP_STEP, false>, 0);
+        }
+    }
     const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;
     switch (a.W) {
     case 1: return occupancy_j<1>(a, pure);

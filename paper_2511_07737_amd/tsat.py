@@ -34,10 +34,10 @@ class TsatError(RuntimeError):
 
 class LaunchConfig(ct.Structure):
     _fields_ = [("fwd_target_blocks", ct.c_int32), ("var_blocks_per_cu", ct.c_int32), ("pure_group", ct.c_int32),
-                ("reserved", ct.c_int32), ("fwd_ms", ct.c_double), ("var_ms", ct.c_double)]
+                ("clause_planes", ct.c_int32), ("fwd_ms", ct.c_double), ("var_ms", ct.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Params(ct.Structure):
@@ -326,8 +326,11 @@ class Solver:
         _check(lib().tsat_get_launch_config(self._h, ct.byref(c)))
         return c
 
-    def set_launch_config(self, fwd_target_blocks=None, var_blocks_per_cu=None, pure_group=None) -> None:
+    def set_launch_config(self, fwd_target_blocks=None, var_blocks_per_cu=None, pure_group=None,
+                          clause_planes=None) -> None:
         c = self.launch_config()
+        if clause_planes is not None:
+            c.clause_planes = int(clause_planes)
         if fwd_target_blocks is not None:
             c.fwd_target_blocks = int(fwd_target_blocks)
         if var_blocks_per_cu is not None:

@@ -31,9 +31,10 @@ def run(cnf_or_list, shape, steps=25, N=100, seed=4):
     return th, m, v, t, bits
 
 
-SHAPES = [dict(fwd_target_blocks=256, var_blocks_per_cu=8, pure_group=1),
-          dict(fwd_target_blocks=4096, var_blocks_per_cu=64, pure_group=4),
-          dict(fwd_target_blocks=1000, var_blocks_per_cu=0, pure_group=2)]
+SHAPES = [dict(fwd_target_blocks=256, var_blocks_per_cu=8, pure_group=1, clause_planes=0),
+          dict(fwd_target_blocks=4096, var_blocks_per_cu=64, pure_group=4, clause_planes=0),
+          dict(fwd_target_blocks=1000, var_blocks_per_cu=0, pure_group=2, clause_planes=1),
+          dict(fwd_target_blocks=512, var_blocks_per_cu=16, pure_group=2, clause_planes=0)]
 
 
 @pytest.mark.parametrize("which", ["planted", "mixed", "batch"])
@@ -64,7 +65,10 @@ def test_autotune_picks_a_candidate_and_keeps_solving(pure):
     # the record group only matters (and is only tuned) for uniform-width stores
     assert c.pure_group in ((1, 2, 4) if pure else (before.pure_group,))
     assert c.fwd_ms > 0 and c.var_ms > 0
-    assert used == 2 * (5 + 5 * (3 if pure else 1))
+    assert c.clause_planes in ((0, 1) if pure else (before.clause_planes,))
+    # forward targets, then blocks per CU with the clause planes on and, off,
+    # with the three record groups (uniform widths only)
+    assert used == 2 * (5 + (5 + 5 * 3 if pure else 5))
     got = s.launch_config()
     assert (got.fwd_target_blocks, got.var_blocks_per_cu, got.pure_group) == \
         (c.fwd_target_blocks, c.var_blocks_per_cu, c.pure_group)
@@ -77,7 +81,7 @@ def test_autotune_picks_a_candidate_and_keeps_solving(pure):
 
 def test_launch_config_errors():
     s = solver_or_skip()
-    for bad in (dict(fwd_target_blocks=0), dict(var_blocks_per_cu=-1), dict(pure_group=3)):
+    for bad in (dict(fwd_target_blocks=0), dict(var_blocks_per_cu=-1), dict(pure_group=3), dict(clause_planes=2)):
         with pytest.raises(tsat.TsatError) as e:
             s.set_launch_config(**bad)
         assert e.value.code == tsat.E_ARG
