@@ -123,6 +123,17 @@ struct VarArgs {
     // occ_mid), and the forward pass's planes of R for these bits
     const uint32_t* occ_cid;  // null: gather the other literals' rows instead
     const uint32_t* planes;   // [Cb][2][2 J] dwords
+    // generic stores: variables with many occurrence words are split into
+    // chunks of records handled by separate waves; their FP64 partial sums
+    // are added in chunk order by one wave per variable, which runs the tail
+    const uint32_t* heavy;    // [V] 1: handled by the chunk kernels; null: none
+    int32_t n_heavy, n_chunks;
+    const uint32_t* hv_var;   // [n_heavy]
+    const uint32_t* hv_chunk; // [n_heavy + 1] first chunk of each heavy variable
+    const uint32_t* ch_var;   // [n_chunks]
+    const uint32_t* ch_beg;   // [n_chunks] word range of the chunk's records
+    const uint32_t* ch_end;   // [n_chunks]
+    double* partial;          // [n_chunks][Np]
 };
 
 struct SelectArgs {

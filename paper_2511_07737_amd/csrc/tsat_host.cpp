@@ -51,7 +51,13 @@ struct Store {
     std::vector<uint32_t> occ_off, occ_mid, occ_data;
     // uniform widths 2 and 3: the same records as clause indices within the bucket
     std::vector<uint32_t> occ_cid;
+    // generic records: variables with more than kHeavyWords occurrence words,
+    // cut at record boundaries into chunks of at most kChunkWords words
+    std::vector<uint32_t> heavy, hv_var, hv_chunk, ch_var, ch_beg, ch_end;
 };
+
+static constexpr uint32_t kHeavyWords = 768;
+static constexpr uint32_t kChunkWords = 512;
 
 static inline uint32_t lit_code(int32_t x, uint32_t base)
 {
@@ -194,6 +200,35 @@ static int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_
                 }
             }
         }
+        if (!pure) {
+            st.heavy.assign((size_t)V, 0u);
+            st.hv_chunk.push_back(0);
+            for (int32_t v = 0; v < V; ++v) {
+                const uint32_t b = st.occ_off[v], e = st.occ_off[v + 1];
+                if (e - b <= kHeavyWords) continue;
+                st.heavy[v] = 1u;
+                st.hv_var.push_back((uint32_t)v);
+                uint32_t q = b, cb = b;
+                while (q < e) {
+                    const uint32_t len = 1u + st.occ_data[q];
+                    if (q > cb && q + len - cb > kChunkWords) {
+                        st.ch_var.push_back((uint32_t)v);
+                        st.ch_beg.push_back(cb);
+                        st.ch_end.push_back(q);
+                        cb = q;
+                    }
+                    q += len;
+                }
+                st.ch_var.push_back((uint32_t)v);
+                st.ch_beg.push_back(cb);
+                st.ch_end.push_back(e);
+                st.hv_chunk.push_back((uint32_t)st.ch_var.size());
+            }
+            if (st.hv_var.empty()) {
+                st.heavy.clear();
+                st.hv_chunk.clear();
+            }
+        }
     } catch (const std::bad_alloc&) {
         return fail(TSAT_E_OOM, "host allocation failed while building the occurrence store");
     }
@@ -229,6 +264,8 @@ struct tsat_solver {
     DBuf occ_off, occ_mid, occ_data, var_inst, info;
     DBuf occ_cid;            // clause-index records (uniform widths 2, 3)
     DBuf planes, planes_scr; // R of every clause in binary, for the step / for evaluations
+    DBuf heavy, hv_var, hv_chunk, ch_var, ch_beg, ch_end; // chunked heavy variables (generic stores)
+    DBuf partial, partial_scr; // FP64 partial sums of the chunks, for the step / for evaluations
 
     // batch
     int32_t N = 0, W = 0, Np = 0;
@@ -470,7 +507,25 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     // step overrides this with its own buffer
     a.occ_cid = plane_path(s, N) ? s->occ_cid.as<uint32_t>() : nullptr;
     a.planes = s->planes_scr.as<uint32_t>();
+    if (s->heavy.p) {
+        a.heavy = s->heavy.as<uint32_t>();
+        a.n_heavy = (int32_t)s->st.hv_var.size();
+        a.n_chunks = (int32_t)s->st.ch_var.size();
+        a.hv_var = s->hv_var.as<uint32_t>();
+        a.hv_chunk = s->hv_chunk.as<uint32_t>();
+        a.ch_var = s->ch_var.as<uint32_t>();
+        a.ch_beg = s->ch_beg.as<uint32_t>();
+        a.ch_end = s->ch_end.as<uint32_t>();
+        a.partial = s->partial_scr.as<double>(); // evaluations; the step uses its own buffer
+    }
     return a;
+}
+
+// FP64 partial rows of the heavy-variable chunks for N candidates
+static int32_t ensure_partial(tsat_solver* s, DBuf& buf, int32_t N)
+{
+    if (!s->heavy.p) return TSAT_OK;
+    return buf.reserve(s->st.ch_var.size() * (size_t)(64 * ((N + 63) / 64)) * sizeof(double), "chunk partial sums");
 }
 
 // the variable-major kernels address literal rows with 32-bit byte offsets
@@ -768,6 +823,19 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     }
     s->planes.release();
     s->planes_scr.release();
+    s->partial.release();
+    s->partial_scr.release();
+    {
+        const Store& t = s->st;
+        DBuf* bufs[] = {&s->heavy, &s->hv_var, &s->hv_chunk, &s->ch_var, &s->ch_beg, &s->ch_end};
+        const std::vector<uint32_t>* src[] = {&t.heavy, &t.hv_var, &t.hv_chunk, &t.ch_var, &t.ch_beg, &t.ch_end};
+        for (int i = 0; i < 6; ++i) {
+            bufs[i]->release();
+            if (src[i]->empty()) continue;
+            RET(bufs[i]->alloc(src[i]->size() * 4, "heavy-variable chunks"));
+            HIPCHK(hipMemcpy(bufs[i]->p, src[i]->data(), src[i]->size() * 4, hipMemcpyHostToDevice));
+        }
+    }
     const size_t ni = (size_t)s->st.n_inst;
     RET(s->info.alloc(ni * sizeof(InstInfo), "instance sizes"));
     HIPCHK(hipMemcpy(s->info.p, s->st.info.data(), ni * sizeof(InstInfo), hipMemcpyHostToDevice));
@@ -859,6 +927,7 @@ static int32_t alloc_batch(tsat_solver* s, int32_t N)
     HIPCHK(launch_fill_u32(s->m.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
     HIPCHK(launch_fill_u32(s->v.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
     if (plane_path(s, N)) RET(ensure_planes(s, s->planes, N, s->stream));
+    RET(ensure_partial(s, s->partial, N));
     s->N = N;
     s->W = W;
     s->Np = Np;
@@ -1053,6 +1122,7 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
     sa.update = 1;
     VarArgs va = var_args(s, p, s->N, s->W, s->Np);
     va.planes = s->planes.as<uint32_t>();
+    if (va.heavy) va.partial = s->partial.as<double>();
     va.tbl = s->table.as<float>();
     va.theta = s->theta.as<float>();
     va.m = s->m.as<float>();
@@ -1220,6 +1290,7 @@ static int32_t eval_rows(tsat_solver* s, const tsat_params& p, const uint64_t* l
         RET(ensure_planes(s, s->planes_scr, N, st));
         planes = s->planes_scr.as<uint32_t>();
     }
+    RET(ensure_partial(s, s->partial_scr, N));
     RET(enqueue_fwd(s, lits, N, s->H_scr.as<uint32_t>(), nullptr, nullptr, st, planes));
     SminArgs a = smin_args(s, p, N, Np);
     a.H = s->H_scr.as<uint32_t>();

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "tsat_device.h"
 #include "tsat_learned.h"
 
@@ -659,6 +661,7 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
     int bad = 0;
 
     for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        if (a.heavy && sload(a.heavy + v)) continue; // the chunk kernels own it
         const VarInst vi = var_instance<OP>(a, v);
         if (vi.frozen) {
             keep_variable<J>(a, v, lane);
@@ -712,6 +715,104 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
         if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
         advance_step(a);
     }
+}
+
+// Heavy variables of generic stores.  Chunk kernel: one wave per chunk of a
+// heavy variable's records sums their table entries (same arithmetic as the
+// generic kernel) into an FP64 partial row.  Tail kernel: one wave per heavy
+// variable adds its partials in chunk order and runs the tail.
+template <int J, int OP>
+__global__ __launch_bounds__(256) void var_heavy_part_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) return;
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const int W = a.W, Np = a.Np;
+    const char* lit_base = (const char*)a.lits_cur;
+    const uint32_t row_bytes = (uint32_t)W * 8u;
+    for (uint32_t ch = wave0; ch < (uint32_t)a.n_chunks; ch += nwaves) {
+        const uint32_t v = sload(a.ch_var + ch);
+        const VarInst vi = var_instance<OP>(a, v);
+        double U[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) U[j] = 0.0;
+        if (!vi.frozen) {
+            const float* tg = a.tbl + (size_t)vi.inst * a.K1 * Np;
+            const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+            uint64_t oP[J], oN[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                oP[j] = sload(ownp + j);
+                oN[j] = sload(ownp + W + j);
+            }
+            uint32_t q = sload(a.ch_beg + ch);
+            const uint32_t qe = sload(a.ch_end + ch), qm = sload(a.occ_mid + v);
+            while (q < qe) {
+                const bool neg = q >= qm;
+                const uint32_t k1 = sload(a.occ_data + q);
+                uint32_t R[J];
+#pragma unroll
+                for (int j = 0; j < J; ++j) R[j] = add_lane_bit(0u, neg ? oN[j] : oP[j]);
+                for (uint32_t e = 0; e < k1; ++e) {
+                    const uint32_t off = sload(a.occ_data + q + 1 + e) * row_bytes;
+                    const uint64_t* row = (const uint64_t*)(lit_base + off);
+#pragma unroll
+                    for (int j = 0; j < J; ++j) R[j] = add_lane_bit(R[j], sload(row + j));
+                }
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    if (j >= W) break;
+                    const double val = (double)tg[R[j] * Np + 64 * j + lane];
+                    U[j] = neg ? U[j] - val : U[j] + val;
+                }
+                q += 1 + k1;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < W) a.partial[(size_t)ch * Np + 64 * j + lane] = U[j];
+    }
+}
+
+template <int J, int OP>
+__global__ __launch_bounds__(256) void var_heavy_tail_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) return;
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const int W = a.W, Np = a.Np;
+    const StepScalars c = load_scalars(a, OP);
+    int bad = 0;
+    for (uint32_t h = wave0; h < (uint32_t)a.n_heavy; h += nwaves) {
+        const uint32_t v = sload(a.hv_var + h);
+        const VarInst vi = var_instance<OP>(a, v);
+        if (vi.frozen) {
+            keep_variable<J>(a, v, lane);
+            continue;
+        }
+        double U[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) U[j] = 0.0;
+        const uint32_t c0 = sload(a.hv_chunk + h), c1 = sload(a.hv_chunk + h + 1);
+        for (uint32_t ch = c0; ch < c1; ++ch) {
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+                if (j < W) U[j] += a.partial[(size_t)ch * Np + 64 * j + lane];
+        }
+        float th[J], mm[J], vv[J];
+        bool valid[J];
+        load_row<J, OP>(a, v, lane, th, mm, vv, valid);
+        bool clamped = false;
+        const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+        const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+        uint64_t oP[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+        var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
+    }
+    if (OP == OP_STEP && ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
 }
 
 // Every clause has the same width k = KO + 1 (KO other literals per record,
@@ -1545,10 +1646,36 @@ static hipError_t launch_var_jm(const VarArgs& a, int op, int blocks, hipStream_
     return hipGetLastError();
 }
 
+template <int J, int OP>
+static hipError_t launch_heavy_op(const VarArgs& a, bool tail, int blocks, hipStream_t st)
+{
+    if (tail) hipLaunchKernelGGL((var_heavy_tail_kernel<J, OP>), dim3(blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((var_heavy_part_kernel<J, OP>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int J>
+static hipError_t launch_heavy(const VarArgs& a, int op, bool tail, int blocks, hipStream_t st)
+{
+    switch (op) {
+    case OP_STEP: return launch_heavy_op<J, OP_STEP>(a, tail, blocks, st);
+    case OP_GRAD: return launch_heavy_op<J, OP_GRAD>(a, tail, blocks, st);
+    default: return launch_heavy_op<J, OP_ADJ>(a, tail, blocks, st);
+    }
+}
+
 template <int J>
 static hipError_t launch_var_j(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
-    return a.var_inst ? launch_var_jm<J, true>(a, op, blocks, st) : launch_var_jm<J, false>(a, op, blocks, st);
+    const bool split = a.heavy && a.n_chunks > 0 && op != OP_BINARIZE;
+    if (split) {
+        // partial sums of the heavy variables, then the light variables, then the heavy tails
+        hipError_t e = launch_heavy<J>(a, op, false, std::max(1, std::min((a.n_chunks + 3) / 4, blocks)), st);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = a.var_inst ? launch_var_jm<J, true>(a, op, blocks, st) : launch_var_jm<J, false>(a, op, blocks, st);
+    if (e != hipSuccess || !split) return e;
+    return launch_heavy<J>(a, op, true, std::max(1, std::min((a.n_heavy + 3) / 4, blocks)), st);
 }
 
 // resident blocks per CU of the kernel a launch with these arguments would use

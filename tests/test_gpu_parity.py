@@ -108,6 +108,30 @@ def test_mixed_widths_and_edge_clauses(solver):
     one_step_parity(solver, mixed_edge_cnf(), 130, 31, 12)
 
 
+def heavy_cnf():
+    """Mixed widths where two variables occur in thousands of clauses: their
+    occurrence records are split into chunks summed by separate waves."""
+    g = np.random.default_rng(17)
+    clauses = []
+    for _ in range(2500):
+        k = int(g.integers(2, 7))
+        vs = g.choice(np.arange(3, 401), size=k, replace=False)
+        clauses.append([int(v) if g.random() < 0.5 else -int(v) for v in vs])
+    for hv, n in ((1, 1500), (2, 300)):
+        for _ in range(n):
+            k = int(g.integers(1, 6))
+            vs = g.choice(np.arange(3, 401), size=k, replace=False)
+            cl = [int(v) if g.random() < 0.5 else -int(v) for v in vs]
+            cl.append(hv if g.random() < 0.5 else -hv)
+            clauses.append(cl)
+    return gen.CNF.from_clauses(400, clauses)
+
+
+@pytest.mark.parametrize("mode", [tsat.MODE_MEAN, tsat.MODE_NONE])
+def test_heavy_variables_split_into_chunks(solver, mode):
+    one_step_parity(solver, heavy_cnf(), 100, 61, 5, p=tsat.default_params(norm_mode=mode))
+
+
 def test_none_mode(solver):
     p = tsat.default_params(norm_mode=tsat.MODE_NONE)
     one_step_parity(solver, gen.planted_ksat(200, 800, 3, seed=5), 64, 41, 3, p=p)
