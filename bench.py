@@ -45,29 +45,45 @@ def make_cnf(w):
     return gen.structured(w["V"], w["C"], seed=w["seed"])
 
 
-def algorithmic_bytes_step_kernel(cnf, N):
-    """Bytes the fused variable-major kernel must move once per launch:
-    theta, m, v read and written (24 B per (variable, candidate)), the own
-    literal rows read and the next ones written (4 x N/8 B per variable),
-    the occurrence store read once (4 B per word: sum over clauses of k^2
-    words) and the two per-variable offsets (8 B)."""
+def uses_clause_planes(cnf, N, planes_on):
+    """The update gathers the forward's planes of R (uniform width 2 or 3, N <= 256)."""
     import numpy as np
 
-    V = cnf.num_vars
+    w = np.unique(cnf.widths())
+    return bool(planes_on) and w.size == 1 and int(w[0]) in (2, 3) and N <= 256
+
+
+def algorithmic_bytes_step_kernel(cnf, N, planes):
+    """Bytes the update step must move once per iteration: theta, m, v read
+    and written (24 B per (variable, candidate)), the next literal rows
+    written (2 rows of N/8 B per variable), the row means (16 B per
+    variable), the record offsets (8 B per variable) and either
+    - with clause planes: the own row (N/8 B per variable), the two planes of
+      every clause (2 x N/8 B per clause) and one clause index per literal
+      (4 B), or
+    - with row gathers: the own rows (2 x N/8 B per variable) and the
+      occurrence store (4 B per word: sum over clauses of k^2 words)."""
+    import numpy as np
+
+    V, C = cnf.num_vars, cnf.num_clauses
     W = (N + 63) // 64
+    common = 24 * V * N + 2 * V * W * 8 + 16 * V + 8 * V
+    if planes:
+        return common + V * W * 8 + 2 * C * W * 8 + 4 * cnf.num_lits
     occ_words = int((cnf.widths().astype(np.int64) ** 2).sum())
-    return 24 * V * N + 4 * V * W * 8 + 4 * occ_words + 8 * V
+    return common + 2 * V * W * 8 + 4 * occ_words
 
 
-def algorithmic_bytes_fwd(cnf, N):
-    """Forward histogram: clause codes (4 B per literal) plus every literal row
-    once (V rows of N/8 B for the values; the complements are derived)."""
+def algorithmic_bytes_fwd(cnf, N, planes):
+    """Forward histogram: clause codes (4 B per literal), every value row once
+    (V rows of N/8 B; the complements are derived) and, with clause planes,
+    the two planes of every clause written (2 x N/8 B per clause)."""
     W = (N + 63) // 64
-    return 4 * cnf.num_lits + cnf.num_vars * W * 8
+    return 4 * cnf.num_lits + cnf.num_vars * W * 8 + (2 * cnf.num_clauses * W * 8 if planes else 0)
 
 
 KERNEL_SOURCES = ["paper_2511_07737_amd/csrc/tsat_kernels.hip", "paper_2511_07737_amd/csrc/tsat_device.h"]
-PROFILE_FILES = {"large": "profiles/var_pure_kernel__planted-3sat_V1e6_C4.1e6_N256.txt",
+PROFILE_FILES = {"large": "profiles/var_plane_kernel__planted-3sat_V1e6_C4.1e6_N256.txt",
                  "structured": "profiles/var_kernel__structured_V5e5_C2.5e6_N128.txt"}
 
 
@@ -171,8 +187,9 @@ def main():
     ms_per_step = 1e3 * sec / args.steps
     value = evals_per_step * args.steps / sec
 
-    step_bytes = algorithmic_bytes_step_kernel(cnf, N)
-    fwd_bytes = algorithmic_bytes_fwd(cnf, N)
+    planes = uses_clause_planes(cnf, N, s.launch_config().clause_planes)
+    step_bytes = algorithmic_bytes_step_kernel(cnf, N, planes)
+    fwd_bytes = algorithmic_bytes_fwd(cnf, N, planes)
     names = ["fwd_hist", "smin_tables", "var_step"]
     dom = int(np.argmax(kms))
     dom_bytes = {0: fwd_bytes, 2: step_bytes}.get(dom)
@@ -197,7 +214,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["name"], "V": cnf.num_vars, "C": cnf.num_clauses, "L": cnf.num_lits, "N": N,
-                   "steps_per_launch_sequence": args.steps},
+                   "steps_per_launch_sequence": args.steps, "launch": s.launch_config().as_dict()},
         "roofline": roofline,
         "kernels_ms": {n: round(x, 5) for n, x in zip(names, kms)},
         "kernel_iters": kiters,
