@@ -11,7 +11,7 @@ resident in HBM before the timed region.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 10]
                        [--workload large|structured|tiny] [--no-cpu-baseline]
-                       [--no-learned] [--calib-copy-mib M]
+                       [--no-learned] [--no-autotune] [--calib-copy-mib M]
 """
 from __future__ import annotations
 
@@ -152,6 +152,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-versus-random start comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -175,6 +176,12 @@ def main():
     s.load(cnf)
     s.init_batch(N, init_logits=gen.normal_logits(cnf.num_vars, N, w["init_seed"]))
     print("[bench] warmup", file=sys.stderr, flush=True)
+    tuned = None
+    if args.warmup > 0 and not args.no_autotune:
+        # launch shapes never change results: tuning iterations are ordinary
+        # (untimed) iterations of the run
+        cfg, used = s.autotune(iters=2)
+        tuned = dict(cfg.as_dict(), iterations=used)
     s.step(args.warmup)
     s.set_timing(True)
     t0 = time.perf_counter()
@@ -214,7 +221,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["name"], "V": cnf.num_vars, "C": cnf.num_clauses, "L": cnf.num_lits, "N": N,
-                   "steps_per_launch_sequence": args.steps, "launch": s.launch_config().as_dict()},
+                   "steps_per_launch_sequence": args.steps, "launch": s.launch_config().as_dict(),
+                   "autotuned": tuned is not None},
         "roofline": roofline,
         "kernels_ms": {n: round(x, 5) for n, x in zip(names, kms)},
         "kernel_iters": kiters,

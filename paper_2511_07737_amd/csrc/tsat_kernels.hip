@@ -1193,7 +1193,8 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
 // other update kernels.
 // ---------------------------------------------------------------------------
 template <int J, int KW, int OP, bool FULL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void var_plane_kernel(VarArgs a)
+// seven waves per SIMD: the register budget of eight would spill to scratch
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) void var_plane_kernel(VarArgs a)
 {
     if (OP == OP_STEP && a.ctrl->stop) {
         copy_bits_on_stop(a);
