@@ -437,6 +437,10 @@ typedef struct {
     int32_t clause_planes;     /* uniform widths 2, 3 and N <= 256: 1 = the forward stores R of every
                                   clause in binary and the update gathers it (one record per
                                   occurrence), 0 = the update gathers the other literals' rows */
+    int32_t window_gather;     /* with clause planes: 1 = the update loads the planes of 64 consecutive
+                                  occurrence records per vector load and transposes their bits across
+                                  the wavefront, 0 = record by record through the scalar cache;
+                                  default 1 */
     double fwd_ms;             /* tsat_autotune output: forward time per iteration of the choice */
     double var_ms;             /* tsat_autotune output: fused update time per iteration of the choice */
 } tsat_launch_config;
@@ -446,16 +450,18 @@ int32_t tsat_get_launch_config(tsat_solver* s, tsat_launch_config* out);
 
 /* Set launch shapes (fwd_ms/var_ms ignored); drops a captured graph.
  * E_ARG outside the documented ranges.  The environment variables
- * TSAT_FWD_TARGET_BLOCKS, TSAT_VAR_BLOCKS_PER_CU, TSAT_PURE_GROUP and
- * TSAT_CLAUSE_PLANES set the initial values of a new solver. */
+ * TSAT_FWD_TARGET_BLOCKS, TSAT_VAR_BLOCKS_PER_CU, TSAT_PURE_GROUP,
+ * TSAT_CLAUSE_PLANES and TSAT_WINDOW_GATHER set the initial values of a new
+ * solver. */
 int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg);
 
 /* Autotuner: times candidate shapes on real iterations of the current batch
  * (`iters` in [1, 64] iterations per candidate, per-kernel HIP-event timing):
  * first the forward work-unit target (256..4096), then the fused update's
  * blocks per CU (auto, 8, 16, 32, 64) with, for uniform-width stores, the
- * clause-plane gather on and off and, without it, the record group (1, 2,
- * 4), compared on forward + update time; keeps the fastest and returns it in *best
+ * clause-plane gather on (by windows and record by record) and off and,
+ * without it, the record group (1, 2, 4), compared on forward + update
+ * time; keeps the fastest and returns it in *best
  * (may be NULL) with the measured times.  The iterations advance the batch
  * (p as in tsat_step, no early stop); *iters_used (may be NULL) receives
  * their number.  Callers that want a fresh start re-initialize the batch. */

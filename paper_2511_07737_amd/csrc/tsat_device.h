@@ -99,6 +99,7 @@ struct VarArgs {
     int32_t pure_k;           // 2..4: every clause has this width and the records
                               // carry no header; 0: generic records
     int32_t group;            // records per scalar-load group in the pure kernel
+    int32_t window;           // clause-plane gather by 64-record windows (vector loads, transposed)
     const uint32_t* occ_off;  // [V+1] offsets into occ_data (words, or records if pure)
     const uint32_t* occ_mid;  // [V] first record of negative occurrences
     const uint32_t* occ_data; // records: [k-1,] the other k-1 literal indices

@@ -290,6 +290,7 @@ struct tsat_solver {
     int32_t var_per_cu = 0;           // variable-major blocks per CU (0: 4 x occupancy)
     int32_t pure_group = 2;           // records per load group, uniform-width stores
     int32_t clause_planes = 1;        // uniform widths 2, 3: backward gathers the forward's planes of R
+    int32_t window_gather = 1;        // clause planes: 64 records per vector load, transposed across the wave
 
     // learned proposal: features and aggregation channels, kept proposal
     DBuf feat, fh[2], fzinv, prop;
@@ -494,6 +495,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.mode = p.norm_mode;
     a.pure_k = s->st.pure_k;
     a.group = s->pure_group;
+    a.window = s->window_gather;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
     a.occ_data = s->occ_data.as<uint32_t>();
@@ -750,6 +752,7 @@ int32_t tsat_create(const tsat_config* cfg, tsat_solver** out)
     s->var_per_cu = std::max(0, env_int("TSAT_VAR_BLOCKS_PER_CU", s->var_per_cu));
     s->pure_group = env_int("TSAT_PURE_GROUP", s->pure_group);
     s->clause_planes = env_int("TSAT_CLAUSE_PLANES", s->clause_planes) != 0;
+    s->window_gather = env_int("TSAT_WINDOW_GATHER", s->window_gather) != 0;
     if (cfg && cfg->stream) {
         s->stream = (hipStream_t)cfg->stream;
     } else {
@@ -1649,6 +1652,7 @@ static int32_t check_launch_config(const tsat_launch_config* c)
     if (c->pure_group != 1 && c->pure_group != 2 && c->pure_group != 4)
         return fail(TSAT_E_ARG, "pure_group must be 1, 2 or 4");
     if (c->clause_planes != 0 && c->clause_planes != 1) return fail(TSAT_E_ARG, "clause_planes must be 0 or 1");
+    if (c->window_gather != 0 && c->window_gather != 1) return fail(TSAT_E_ARG, "window_gather must be 0 or 1");
     return TSAT_OK;
 }
 
@@ -1661,6 +1665,7 @@ int32_t tsat_get_launch_config(tsat_solver* s, tsat_launch_config* out)
     out->var_blocks_per_cu = s->var_per_cu;
     out->pure_group = s->pure_group;
     out->clause_planes = s->clause_planes;
+    out->window_gather = s->window_gather;
     return TSAT_OK;
 }
 
@@ -1676,6 +1681,7 @@ int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg)
     s->var_per_cu = cfg->var_blocks_per_cu;
     s->pure_group = cfg->pure_group;
     s->clause_planes = cfg->clause_planes;
+    s->window_gather = cfg->window_gather;
     if (s->N > 0 && plane_path(s, s->N)) RET(ensure_planes(s, s->planes, s->N, s->stream));
     return TSAT_OK;
 }
@@ -1732,24 +1738,29 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
     static const int kGroups[] = {1, 2, 4};
     double best_var = 1e30, best_sum = 1e30;
     tsat_launch_config pick = cur;
-    // with clause planes the record group does not apply; the forward writes
-    // the planes, so the shapes are compared on forward + update time
+    // with clause planes the record group does not apply (the planes come in
+    // by 64-record windows or record by record); the forward writes the
+    // planes, so the shapes are compared on forward + update time
     for (int cp = planes_apply ? 1 : 0; cp >= 0; --cp) {
         const int ngroups = (pure && !cp) ? 3 : 1;
+        const int nwin = cp ? 2 : 1;
         for (int pc : kPerCu) {
             for (int gi = 0; gi < ngroups; ++gi) {
-                tsat_launch_config c = cur;
-                c.var_blocks_per_cu = pc;
-                c.pure_group = ngroups > 1 ? kGroups[gi] : cur.pure_group;
-                c.clause_planes = planes_apply ? cp : cur.clause_planes;
-                RET(tsat_set_launch_config(s, &c));
-                RET(time_iterations(s, iters, p, ms));
-                used += iters;
-                if (ms[0] + ms[2] < best_sum) {
-                    best_sum = ms[0] + ms[2];
-                    best_var = ms[2];
-                    best_fwd = ms[0];
-                    pick = c;
+                for (int wi = 0; wi < nwin; ++wi) {
+                    tsat_launch_config c = cur;
+                    c.var_blocks_per_cu = pc;
+                    c.pure_group = ngroups > 1 ? kGroups[gi] : cur.pure_group;
+                    c.clause_planes = planes_apply ? cp : cur.clause_planes;
+                    c.window_gather = nwin > 1 ? 1 - wi : cur.window_gather;
+                    RET(tsat_set_launch_config(s, &c));
+                    RET(time_iterations(s, iters, p, ms));
+                    used += iters;
+                    if (ms[0] + ms[2] < best_sum) {
+                        best_sum = ms[0] + ms[2];
+                        best_var = ms[2];
+                        best_fwd = ms[0];
+                        pick = c;
+                    }
                 }
             }
         }

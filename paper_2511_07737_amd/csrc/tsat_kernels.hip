@@ -1180,6 +1180,58 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
     }
 }
 
+// U of one variable row from the plane counts: cnt[sign][r - 1][j] = the
+// records of that sign whose clause has R >= r at candidate 64 j + lane
+// (r = 3: R = 3), dp / dn the record counts, oP the variable's own bits and
+// my_gt the lane-private dL/dR table ([r][j][lane]).  The order of
+// operations is that of the row-gather kernels, so that every gather gives
+// identical results: per count O of the other true literals, the positive
+// occurrences (R = x + O) and the negative ones (R = 1 - x + O), x the
+// lane's own value.
+template <int J, int KW>
+__device__ __forceinline__ void plane_u(const uint32_t (&cnt)[2][KW][J], uint32_t dp, uint32_t dn,
+                                        const uint64_t (&oP)[J], const float* my_gt, uint32_t lane, double (&U)[J])
+{
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t x = add_lane_bit(0u, oP[j]);
+        uint32_t gep[KW + 2], gen[KW + 2]; // records with R >= r, per sign
+        gep[0] = dp;
+        gen[0] = dn;
+#pragma unroll
+        for (int r = 1; r <= KW; ++r) {
+            gep[r] = cnt[0][r - 1][j];
+            gen[r] = cnt[1][r - 1][j];
+        }
+        gep[KW + 1] = 0u;
+        gen[KW + 1] = 0u;
+        float u = 0.f;
+#pragma unroll
+        for (int O = 0; O < KW; ++O) {
+            const float np = (float)(x ? gep[O + 1] - gep[O + 2] : gep[O] - gep[O + 1]);
+            const float nn = (float)(x ? gen[O] - gen[O + 1] : gen[O + 1] - gen[O + 2]);
+            const float g_lo = my_gt[(O * J + j) * 64 + lane];
+            const float g_hi = my_gt[((O + 1) * J + j) * 64 + lane];
+            const float gp = x ? g_hi : g_lo;
+            const float gn = x ? g_lo : g_hi;
+            u = fmaf(np, gp, u);
+            u = fmaf(-nn, gn, u);
+        }
+        U[j] = (double)u;
+    }
+}
+
+// Lane-private copy of an instance's dL/dR table, [r][j][lane].
+template <int J, int K1>
+__device__ __forceinline__ void load_gt(const VarArgs& a, uint32_t inst, float* my_gt, uint32_t lane)
+{
+    const float* tg = a.tbl + (size_t)inst * K1 * a.Np;
+#pragma unroll
+    for (int r = 0; r < K1; ++r)
+#pragma unroll
+        for (int j = 0; j < J; ++j) my_gt[(r * J + j) * 64 + lane] = (j < a.W) ? tg[(size_t)r * a.Np + 64 * j + lane] : 0.f;
+}
+
 // ---------------------------------------------------------------------------
 // Uniform-width update with the clause-plane gather (widths 2 and 3).
 //
@@ -1316,6 +1368,170 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
             U[j] = (double)u;
         }
         var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
+    }
+    if (OP == OP_STEP) {
+        if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
+        advance_step(a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Clause-plane update by record windows (uniform widths 2 and 3).
+//
+// The same counts as var_plane_kernel, gathered through the vector memory
+// path: a wave owns a chunk of consecutive variables, whose occurrence
+// records are consecutive too, and takes them 64 at a time: lane r loads
+// record r's clause index (one coalesced load) and that clause's planes (one
+// random 16 J-byte load per lane), then each of the 2 J plane words is
+// transposed across the wave (a 64 x 64 bit matrix: afterwards lane l holds,
+// per word, one bit per record for candidate 64 j + l).  A variable's counts
+// are popcounts of these words under the mask of its records' window bits;
+// a variable whose records run past the window takes the next window and
+// adds.  Every record is loaded once.  U and the tail are those of
+// var_plane_kernel, so the results are identical.
+// ---------------------------------------------------------------------------
+
+// 64 x 64 bit-matrix transpose across the wave: lane i holds row i (bit c is
+// element (i, c)); afterwards lane c holds column c (bit i is element (i, c)).
+// Stage b (32, 16, ..., 1) exchanges the off-diagonal b x b blocks of lanes i
+// and i ^ b: the lane with bit b clear keeps the columns with bit b clear and
+// takes its partner's, shifted up by b; the other keeps the columns with bit
+// b set and takes its partner's, shifted down.  Below b = 32 the blocks lie
+// inside 32-bit halves, so the shift is a rotation whose wrapped bits fall
+// under the kept mask.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane)
+{
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {
+        const bool up = lane & 32u;
+        const uint32_t got = (uint32_t)__shfl_xor((int)(up ? lo : hi), 32);
+        if (up) lo = got;
+        else hi = got;
+    }
+    const uint32_t keep_lo[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        const uint32_t b = 16u >> st;
+        const bool up = lane & b;
+        const uint32_t keep = up ? ~keep_lo[st] : keep_lo[st];
+        const uint32_t rot = up ? b : 32u - b; // rotate right: down by b, or up by b
+        const uint32_t plo = (uint32_t)__shfl_xor((int)lo, (int)b);
+        const uint32_t phi = (uint32_t)__shfl_xor((int)hi, (int)b);
+        lo = (keep & lo) | (~keep & __builtin_amdgcn_alignbit(plo, plo, rot));
+        hi = (keep & hi) | (~keep & __builtin_amdgcn_alignbit(phi, phi, rot));
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Planes of records [w, w + 64) (records at or past `end` read as zero),
+// transposed: t[p][j] bit r = plane p, word j, candidate bit of record w + r.
+template <int J>
+__device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane,
+                                            uint64_t (&t)[2][J])
+{
+    const uint32_t rec = w + lane;
+    const bool ok = rec < end;
+    const uint32_t id = ok ? a.occ_cid[rec] : 0u;
+    const uint4* pl = (const uint4*)a.planes + (size_t)id * J; // 2 J words: [plane][word]
+    uint64_t wd[2 * J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        const uint4 q = ok ? pl[k] : make_uint4(0u, 0u, 0u, 0u);
+        wd[2 * k] = ((uint64_t)q.y << 32) | q.x;
+        wd[2 * k + 1] = ((uint64_t)q.w << 32) | q.z;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int j = 0; j < J; ++j) t[p][j] = transpose64(wd[p * J + j], lane);
+}
+
+// bits [lo, hi) of a 64-bit word, 0 <= lo < hi <= 64
+__device__ __forceinline__ uint64_t bit_range(uint32_t lo, uint32_t hi)
+{
+    const uint64_t below_hi = hi >= 64u ? ~0ull : ((1ull << hi) - 1ull);
+    return below_hi & ~((1ull << lo) - 1ull);
+}
+
+template <int J, int KW, int OP, bool FULL>
+__global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) {
+        copy_bits_on_stop(a);
+        return;
+    }
+    constexpr int K1 = KW + 1; // R in 0..KW
+    constexpr uint32_t kChunk = 16; // variables per wave work item
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const uint32_t V = (uint32_t)a.V;
+    const int W = a.W;
+    const StepScalars c = load_scalars(a, OP);
+    __shared__ float s_gt[4][K1 * J * 64];
+    float* my_gt = s_gt[threadIdx.x / 64u];
+    uint32_t gt_inst = 0xffffffffu;
+    int bad = 0;
+    const uint32_t nchunks = (V + kChunk - 1) / kChunk;
+
+    for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
+        const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
+        const uint32_t rend = sload(a.occ_off + ve); // end of the chunk's records
+        uint32_t w = sload(a.occ_off + vb);        // current window [w, w + 64)
+        uint64_t t[2][J];
+        load_window<J>(a, w, rend, lane, t);
+        for (uint32_t v = vb; v < ve; ++v) {
+            const VarInst vi = var_instance<OP>(a, v);
+            if (vi.frozen) {
+                keep_variable<J>(a, v, lane);
+                continue;
+            }
+            if (vi.inst != gt_inst) {
+                gt_inst = vi.inst;
+                load_gt<J, K1>(a, vi.inst, my_gt, lane);
+            }
+            float th[J], mm[J], vv[J];
+            bool valid[J];
+            load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
+            bool clamped = false;
+            const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+            const uint32_t r0 = sload(a.occ_off + v), rm = sload(a.occ_mid + v), r1 = sload(a.occ_off + v + 1);
+            uint32_t cnt[2][KW][J];
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+                for (int r = 0; r < KW; ++r)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) cnt[sg][r][j] = 0;
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                uint32_t q = sg ? rm : r0;
+                const uint32_t e = sg ? r1 : rm;
+                while (q < e) { // wave-uniform
+                    if (q >= w + 64u) {
+                        w = q;
+                        load_window<J>(a, w, rend, lane, t);
+                    }
+                    const uint32_t hi = e < w + 64u ? e : w + 64u;
+                    const uint64_t m = bit_range(q - w, hi - w);
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const uint64_t b0 = t[0][j], b1 = t[1][j];
+                        cnt[sg][0][j] += (uint32_t)__popcll((b0 | b1) & m); // R >= 1
+                        cnt[sg][1][j] += (uint32_t)__popcll(b1 & m);        // R >= 2
+                        if constexpr (KW == 3) cnt[sg][2][j] += (uint32_t)__popcll(b0 & b1 & m); // R = 3
+                    }
+                    q = hi;
+                }
+            }
+            const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+            uint64_t oP[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+            double U[J];
+            plane_u<J, KW>(cnt, rm - r0, r1 - rm, oP, my_gt, lane, U);
+            var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
+        }
     }
     if (OP == OP_STEP) {
         if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
@@ -1746,13 +1962,20 @@ static hipError_t launch_pure_j(const VarArgs& a, int op, int blocks, hipStream_
     }
 }
 
+template <int J, int KW, int OP, bool FULL>
+static auto plane_kernel_ptr(bool window)
+{
+    return window ? &var_window_kernel<J, KW, OP, FULL> : &var_plane_kernel<J, KW, OP, FULL>;
+}
+
 template <int J, int KW, bool FULL>
 static hipError_t launch_plane_jkf(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
+    const bool win = a.window != 0;
     switch (op) {
-    case OP_STEP: hipLaunchKernelGGL((var_plane_kernel<J, KW, OP_STEP, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
-    case OP_GRAD: hipLaunchKernelGGL((var_plane_kernel<J, KW, OP_GRAD, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((var_plane_kernel<J, KW, OP_ADJ, FULL>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_STEP: hipLaunchKernelGGL((plane_kernel_ptr<J, KW, OP_STEP, FULL>(win)), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_GRAD: hipLaunchKernelGGL((plane_kernel_ptr<J, KW, OP_GRAD, FULL>(win)), dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((plane_kernel_ptr<J, KW, OP_ADJ, FULL>(win)), dim3(blocks), dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
 }
@@ -1811,11 +2034,11 @@ static int occupancy_j(const VarArgs& a, bool pure)
 int var_occupancy(const VarArgs& a, int op)
 {
     if (a.occ_cid && a.planes && op != OP_BINARIZE && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
-        const bool k2 = a.pure_k == 2;
+        const bool k2 = a.pure_k == 2, win = a.window != 0;
         switch (a.W) {
-        case 1: return k2 ? occupancy_of(var_plane_kernel<1, 2, OP_STEP, false>, 0) : occupancy_of(var_plane_kernel<1, 3, OP_STEP, false>, 0);
-        case 2: return k2 ? occupancy_of(var_plane_kernel<2, 2, OP_STEP, false>, 0) : occupancy_of(var_plane_kernel<2, 3, OP_STEP, false>, 0);
-        default: return k2 ? occupancy_of(var_plane_kernel<4, 2, OP_STEP, false>, 0) : occupancy_of(var_plane_kernel<4, 3, OP_STEP, false>, 0);
+        case 1: return occupancy_of(k2 ? plane_kernel_ptr<1, 2, OP_STEP, false>(win) : plane_kernel_ptr<1, 3, OP_STEP, false>(win), 0);
+        case 2: return occupancy_of(k2 ? plane_kernel_ptr<2, 2, OP_STEP, false>(win) : plane_kernel_ptr<2, 3, OP_STEP, false>(win), 0);
+        default: return occupancy_of(k2 ? plane_kernel_ptr<4, 2, OP_STEP, false>(win) : plane_kernel_ptr<4, 3, OP_STEP, false>(win), 0);
         }
     }
     const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;

@@ -34,7 +34,8 @@ class TsatError(RuntimeError):
 
 class LaunchConfig(ct.Structure):
     _fields_ = [("fwd_target_blocks", ct.c_int32), ("var_blocks_per_cu", ct.c_int32), ("pure_group", ct.c_int32),
-                ("clause_planes", ct.c_int32), ("fwd_ms", ct.c_double), ("var_ms", ct.c_double)]
+                ("clause_planes", ct.c_int32), ("window_gather", ct.c_int32), ("fwd_ms", ct.c_double),
+                ("var_ms", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -327,10 +328,12 @@ class Solver:
         return c
 
     def set_launch_config(self, fwd_target_blocks=None, var_blocks_per_cu=None, pure_group=None,
-                          clause_planes=None) -> None:
+                          clause_planes=None, window_gather=None) -> None:
         c = self.launch_config()
         if clause_planes is not None:
             c.clause_planes = int(clause_planes)
+        if window_gather is not None:
+            c.window_gather = int(window_gather)
         if fwd_target_blocks is not None:
             c.fwd_target_blocks = int(fwd_target_blocks)
         if var_blocks_per_cu is not None:

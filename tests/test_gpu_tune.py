@@ -33,7 +33,8 @@ def run(cnf_or_list, shape, steps=25, N=100, seed=4):
 
 SHAPES = [dict(fwd_target_blocks=256, var_blocks_per_cu=8, pure_group=1, clause_planes=0),
           dict(fwd_target_blocks=4096, var_blocks_per_cu=64, pure_group=4, clause_planes=0),
-          dict(fwd_target_blocks=1000, var_blocks_per_cu=0, pure_group=2, clause_planes=1),
+          dict(fwd_target_blocks=1000, var_blocks_per_cu=0, pure_group=2, clause_planes=1, window_gather=1),
+          dict(fwd_target_blocks=777, var_blocks_per_cu=32, pure_group=2, clause_planes=1, window_gather=0),
           dict(fwd_target_blocks=512, var_blocks_per_cu=16, pure_group=2, clause_planes=0)]
 
 
@@ -66,9 +67,10 @@ def test_autotune_picks_a_candidate_and_keeps_solving(pure):
     assert c.pure_group in ((1, 2, 4) if pure else (before.pure_group,))
     assert c.fwd_ms > 0 and c.var_ms > 0
     assert c.clause_planes in ((0, 1) if pure else (before.clause_planes,))
-    # forward targets, then blocks per CU with the clause planes on and, off,
-    # with the three record groups (uniform widths only)
-    assert used == 2 * (5 + (5 + 5 * 3 if pure else 5))
+    # forward targets, then blocks per CU with the clause planes on (by
+    # windows and by records) and, off, with the three record groups (uniform
+    # widths only)
+    assert used == 2 * (5 + (5 * 2 + 5 * 3 if pure else 5))
     got = s.launch_config()
     assert (got.fwd_target_blocks, got.var_blocks_per_cu, got.pure_group) == \
         (c.fwd_target_blocks, c.var_blocks_per_cu, c.pure_group)
