@@ -49,6 +49,7 @@ struct Store {
     // pure_k in 2..4): record offsets of header-less records of k-1 codes.
     int32_t pure_k = 0;
     std::vector<uint32_t> occ_off, occ_mid, occ_data;
+    uint64_t max_sign_deg = 0; // most records of one variable and sign
     // uniform widths 2 and 3: the same records as clause indices within the bucket
     std::vector<uint32_t> occ_cid;
     // generic records: variables with more than kHeavyWords occurrence words,
@@ -163,6 +164,7 @@ static int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_
         for (int32_t v = 0; v < V; ++v) {
             st.occ_off[v] = (uint32_t)total;
             st.occ_mid[v] = (uint32_t)(total + wpos[v]);
+            st.max_sign_deg = std::max(st.max_sign_deg, std::max(wpos[v], wneg[v]));
             total += wpos[v] + wneg[v];
             if (total > 0xffffffffull) return fail(TSAT_E_ARG, "occurrence store exceeds 2^32 words");
         }
@@ -495,7 +497,8 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.mode = p.norm_mode;
     a.pure_k = s->st.pure_k;
     a.group = s->pure_group;
-    a.window = s->window_gather;
+    // the window gather keeps its counts in 16-bit halves
+    a.window = s->window_gather && s->st.max_sign_deg < 65536;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
     a.occ_data = s->occ_data.as<uint32_t>();

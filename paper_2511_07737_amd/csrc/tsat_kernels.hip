@@ -1180,17 +1180,17 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
     }
 }
 
-// U of one variable row from the plane counts: cnt[sign][r - 1][j] = the
-// records of that sign whose clause has R >= r at candidate 64 j + lane
-// (r = 3: R = 3), dp / dn the record counts, oP the variable's own bits and
-// my_gt the lane-private dL/dR table ([r][j][lane]).  The order of
-// operations is that of the row-gather kernels, so that every gather gives
-// identical results: per count O of the other true literals, the positive
-// occurrences (R = x + O) and the negative ones (R = 1 - x + O), x the
-// lane's own value.
+// U of one variable row from packed plane counts: cnt[r - 1][j] holds, for
+// candidate 64 j + lane, the positive records whose clause has R >= r in its
+// low 16 bits and the negative ones in its high 16 bits (r = 3: R = 3); dp /
+// dn are the record counts, oP the variable's own bits and my_gt the
+// lane-private dL/dR table ([r][j][lane]).  The order of operations is that
+// of the other uniform-width gathers, so that every gather gives identical
+// results: per count O of the other true literals, the positive occurrences
+// (R = x + O) and the negative ones (R = 1 - x + O), x the lane's own value.
 template <int J, int KW>
-__device__ __forceinline__ void plane_u(const uint32_t (&cnt)[2][KW][J], uint32_t dp, uint32_t dn,
-                                        const uint64_t (&oP)[J], const float* my_gt, uint32_t lane, double (&U)[J])
+__device__ __forceinline__ void plane_u(const uint32_t (&cnt)[KW][J], uint32_t dp, uint32_t dn, const uint64_t (&oP)[J],
+                                        const float* my_gt, uint32_t lane, double (&U)[J])
 {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -1200,8 +1200,8 @@ __device__ __forceinline__ void plane_u(const uint32_t (&cnt)[2][KW][J], uint32_
         gen[0] = dn;
 #pragma unroll
         for (int r = 1; r <= KW; ++r) {
-            gep[r] = cnt[0][r - 1][j];
-            gen[r] = cnt[1][r - 1][j];
+            gep[r] = cnt[r - 1][j] & 0xffffu;
+            gen[r] = cnt[r - 1][j] >> 16;
         }
         gep[KW + 1] = 0u;
         gen[KW + 1] = 0u;
@@ -1424,10 +1424,11 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane)
 }
 
 // Planes of records [w, w + 64) (records at or past `end` read as zero),
-// transposed: t[p][j] bit r = plane p, word j, candidate bit of record w + r.
+// transposed into the wave's LDS window: win[(p J + j) 64 + lane] bit r =
+// plane p, word j, candidate bit of record w + r (lane-private slots, so the
+// wave needs no barrier).
 template <int J>
-__device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane,
-                                            uint64_t (&t)[2][J])
+__device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane, uint64_t* win)
 {
     const uint32_t rec = w + lane;
     const bool ok = rec < end;
@@ -1443,7 +1444,7 @@ __device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int j = 0; j < J; ++j) t[p][j] = transpose64(wd[p * J + j], lane);
+        for (int j = 0; j < J; ++j) win[(p * J + j) * 64 + lane] = transpose64(wd[p * J + j], lane);
 }
 
 // bits [lo, hi) of a 64-bit word, 0 <= lo < hi <= 64
@@ -1460,8 +1461,8 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
         copy_bits_on_stop(a);
         return;
     }
-    constexpr int K1 = KW + 1; // R in 0..KW
-    constexpr uint32_t kChunk = 16; // variables per wave work item
+    constexpr int K1 = KW + 1;     // R in 0..KW
+    constexpr uint32_t kChunk = 4; // variables per wave work item (measured best of 2, 4, 8, 16)
     const uint32_t lane = __lane_id();
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
     const uint32_t nwaves = uniform(gridDim.x * 4u);
@@ -1469,7 +1470,9 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
     const int W = a.W;
     const StepScalars c = load_scalars(a, OP);
     __shared__ float s_gt[4][K1 * J * 64];
+    __shared__ uint64_t s_win[4][2 * J * 64]; // each wave's transposed record window
     float* my_gt = s_gt[threadIdx.x / 64u];
+    uint64_t* my_win = s_win[threadIdx.x / 64u];
     uint32_t gt_inst = 0xffffffffu;
     int bad = 0;
     const uint32_t nchunks = (V + kChunk - 1) / kChunk;
@@ -1477,9 +1480,8 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
     for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
         const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
         const uint32_t rend = sload(a.occ_off + ve); // end of the chunk's records
-        uint32_t w = sload(a.occ_off + vb);        // current window [w, w + 64)
-        uint64_t t[2][J];
-        load_window<J>(a, w, rend, lane, t);
+        uint32_t w = 0;                              // window [w, w + 64), once loaded
+        bool loaded = false;
         for (uint32_t v = vb; v < ve; ++v) {
             const VarInst vi = var_instance<OP>(a, v);
             if (vi.frozen) {
@@ -1490,40 +1492,42 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
                 gt_inst = vi.inst;
                 load_gt<J, K1>(a, vi.inst, my_gt, lane);
             }
+            const uint32_t r0 = sload(a.occ_off + v), rm = sload(a.occ_mid + v), r1 = sload(a.occ_off + v + 1);
+            // counts per level r and word j: positive records in the low
+            // 16 bits, negative in the high (the host keeps every variable
+            // below 2^16 records per sign on this path)
+            uint32_t cnt[KW][J];
+#pragma unroll
+            for (int r = 0; r < KW; ++r)
+#pragma unroll
+                for (int j = 0; j < J; ++j) cnt[r][j] = 0;
+            for (uint32_t q = r0; q < r1;) { // wave-uniform
+                if (!loaded || q - w >= 64u) {
+                    w = q;
+                    loaded = true;
+                    load_window<J>(a, w, rend, lane, my_win);
+                }
+                const uint32_t hi = r1 < w + 64u ? r1 : w + 64u;
+                const uint64_t mp = q < rm ? bit_range(q - w, (hi < rm ? hi : rm) - w) : 0ull;
+                const uint64_t mn = hi > rm ? bit_range((q > rm ? q : rm) - w, hi - w) : 0ull;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint64_t b0 = my_win[j * 64 + lane], b1 = my_win[(J + j) * 64 + lane];
+                    const uint64_t b01 = b0 | b1; // R >= 1 (b1: R >= 2)
+                    cnt[0][j] += (uint32_t)__popcll(b01 & mp) + ((uint32_t)__popcll(b01 & mn) << 16);
+                    cnt[1][j] += (uint32_t)__popcll(b1 & mp) + ((uint32_t)__popcll(b1 & mn) << 16);
+                    if constexpr (KW == 3) { // R = 3
+                        const uint64_t b3 = b0 & b1;
+                        cnt[2][j] += (uint32_t)__popcll(b3 & mp) + ((uint32_t)__popcll(b3 & mn) << 16);
+                    }
+                }
+                q = hi;
+            }
             float th[J], mm[J], vv[J];
             bool valid[J];
             load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
             bool clamped = false;
             const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
-            const uint32_t r0 = sload(a.occ_off + v), rm = sload(a.occ_mid + v), r1 = sload(a.occ_off + v + 1);
-            uint32_t cnt[2][KW][J];
-#pragma unroll
-            for (int sg = 0; sg < 2; ++sg)
-#pragma unroll
-                for (int r = 0; r < KW; ++r)
-#pragma unroll
-                    for (int j = 0; j < J; ++j) cnt[sg][r][j] = 0;
-#pragma unroll
-            for (int sg = 0; sg < 2; ++sg) {
-                uint32_t q = sg ? rm : r0;
-                const uint32_t e = sg ? r1 : rm;
-                while (q < e) { // wave-uniform
-                    if (q >= w + 64u) {
-                        w = q;
-                        load_window<J>(a, w, rend, lane, t);
-                    }
-                    const uint32_t hi = e < w + 64u ? e : w + 64u;
-                    const uint64_t m = bit_range(q - w, hi - w);
-#pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        const uint64_t b0 = t[0][j], b1 = t[1][j];
-                        cnt[sg][0][j] += (uint32_t)__popcll((b0 | b1) & m); // R >= 1
-                        cnt[sg][1][j] += (uint32_t)__popcll(b1 & m);        // R >= 2
-                        if constexpr (KW == 3) cnt[sg][2][j] += (uint32_t)__popcll(b0 & b1 & m); // R = 3
-                    }
-                    q = hi;
-                }
-            }
             const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
             uint64_t oP[J];
 #pragma unroll
