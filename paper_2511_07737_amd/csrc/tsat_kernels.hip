@@ -65,8 +65,9 @@ template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x)
 {
     const uint64_t u = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    // every lane has a source lane under these patterns, so no old value is needed
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
@@ -1155,20 +1156,21 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
         for (int j = 0; j < J; ++j) {
             // own value of this lane's candidate
             const uint32_t x = BATCHED ? (uint32_t)(oP[j] >> lane) & 1u : add_lane_bit(0u, oP[j]);
-            float u = 0.f;
+            // records with exactly O other literals true, per sign; a
+            // positive occurrence has R = x + O, a negative one R = 1 - x + O
+            int32_t np[KO + 1], nn[KO + 1];
 #pragma unroll
             for (int O = 0; O <= KO; ++O) {
-                const uint32_t cp_hi = (O < KO) ? cnt[0][O][j] : 0u, cn_hi = (O < KO) ? cnt[1][O][j] : 0u;
-                const uint32_t cp_lo = (O == 0) ? dp : cnt[0][O - 1][j];
-                const uint32_t cn_lo = (O == 0) ? dn : cnt[1][O - 1][j];
-                const float np = (float)(cp_lo - cp_hi), nn = (float)(cn_lo - cn_hi);
-                // positive occurrence: R = x + O; negative: R = (1 - x) + O
-                const float g_lo = GT_LDS ? my_gt[(O * J + j) * 64 + lane] : gt[GT_LDS ? 0 : O][j];
-                const float g_hi = GT_LDS ? my_gt[((O + 1) * J + j) * 64 + lane] : gt[GT_LDS ? 0 : O + 1][j];
-                const float gp = x ? g_hi : g_lo;
-                const float gn = x ? g_lo : g_hi;
-                u = fmaf(np, gp, u);
-                u = fmaf(-nn, gn, u);
+                np[O] = (int32_t)(((O == 0) ? dp : cnt[0][O - 1][j]) - ((O < KO) ? cnt[0][O][j] : 0u));
+                nn[O] = (int32_t)(((O == 0) ? dn : cnt[1][O - 1][j]) - ((O < KO) ? cnt[1][O][j] : 0u));
+            }
+            float u = 0.f;
+#pragma unroll
+            for (int r = 0; r <= KO + 1; ++r) {
+                const int32_t ep = x ? (r >= 1 ? np[r - 1] : 0) : (r <= KO ? np[r] : 0);
+                const int32_t en = x ? (r <= KO ? nn[r] : 0) : (r >= 1 ? nn[r - 1] : 0);
+                const float t = GT_LDS ? my_gt[(r * J + j) * 64 + lane] : gt[GT_LDS ? 0 : r][j];
+                u = fmaf((float)(ep - en), t, u);
             }
             U[j] = (double)u;
         }
@@ -1183,39 +1185,25 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
 // U of one variable row from packed plane counts: cnt[r - 1][j] holds, for
 // candidate 64 j + lane, the positive records whose clause has R >= r in its
 // low 16 bits and the negative ones in its high 16 bits (r = 3: R = 3); dp /
-// dn are the record counts, oP the variable's own bits and my_gt the
-// lane-private dL/dR table ([r][j][lane]).  The order of operations is that
-// of the other uniform-width gathers, so that every gather gives identical
-// results: per count O of the other true literals, the positive occurrences
-// (R = x + O) and the negative ones (R = 1 - x + O), x the lane's own value.
+// dn are the record counts and my_gt the lane-private dL/dR table
+// ([r][j][lane]).  U = sum over r of (positive - negative records with R = r)
+// dL/dR[r], in the order of r as in the other uniform-width gathers, so that
+// every gather gives identical results.
 template <int J, int KW>
-__device__ __forceinline__ void plane_u(const uint32_t (&cnt)[KW][J], uint32_t dp, uint32_t dn, const uint64_t (&oP)[J],
-                                        const float* my_gt, uint32_t lane, double (&U)[J])
+__device__ __forceinline__ void plane_u(const uint32_t (&cnt)[KW][J], uint32_t dp, uint32_t dn, const float* my_gt,
+                                        uint32_t lane, double (&U)[J])
 {
+    const uint32_t total = dp | (dn << 16);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const uint32_t x = add_lane_bit(0u, oP[j]);
-        uint32_t gep[KW + 2], gen[KW + 2]; // records with R >= r, per sign
-        gep[0] = dp;
-        gen[0] = dn;
-#pragma unroll
-        for (int r = 1; r <= KW; ++r) {
-            gep[r] = cnt[r - 1][j] & 0xffffu;
-            gen[r] = cnt[r - 1][j] >> 16;
-        }
-        gep[KW + 1] = 0u;
-        gen[KW + 1] = 0u;
         float u = 0.f;
 #pragma unroll
-        for (int O = 0; O < KW; ++O) {
-            const float np = (float)(x ? gep[O + 1] - gep[O + 2] : gep[O] - gep[O + 1]);
-            const float nn = (float)(x ? gen[O] - gen[O + 1] : gen[O + 1] - gen[O + 2]);
-            const float g_lo = my_gt[(O * J + j) * 64 + lane];
-            const float g_hi = my_gt[((O + 1) * J + j) * 64 + lane];
-            const float gp = x ? g_hi : g_lo;
-            const float gn = x ? g_lo : g_hi;
-            u = fmaf(np, gp, u);
-            u = fmaf(-nn, gn, u);
+        for (int r = 0; r <= KW; ++r) {
+            // records with R = r, both signs at once (no borrow: each half of
+            // the minuend is at least that of the subtrahend)
+            const uint32_t e = (r == 0 ? total : cnt[r - 1][j]) - (r < KW ? cnt[r][j] : 0u);
+            const int32_t d = (int32_t)(e & 0xffffu) - (int32_t)(e >> 16);
+            u = fmaf((float)d, my_gt[(r * J + j) * 64 + lane], u);
         }
         U[j] = (double)u;
     }
@@ -1331,10 +1319,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
             }
         }
         const uint32_t dp = rm - r0, dn = r1 - rm;
-        // U in the same order of operations as the row-gather kernels (so
-        // that the two gathers give identical results): per count O of the
-        // other true literals, the positive occurrences (R = x + O) and the
-        // negative ones (R = 1 - x + O), x the lane's own value
+        // U as in the other uniform-width gathers (identical results): the
+        // sum over r of (positive - negative records with R = r) dL/dR[r]
         const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
         uint64_t oP[J];
 #pragma unroll
@@ -1342,28 +1328,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         double U[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const uint32_t x = add_lane_bit(0u, oP[j]);
-            uint32_t gep[KW + 2], gen[KW + 2]; // records with R >= r, per sign
-            gep[0] = dp;
-            gen[0] = dn;
-#pragma unroll
-            for (int r = 1; r <= KW; ++r) {
-                gep[r] = cnt[0][r - 1][j];
-                gen[r] = cnt[1][r - 1][j];
-            }
-            gep[KW + 1] = 0u;
-            gen[KW + 1] = 0u;
             float u = 0.f;
 #pragma unroll
-            for (int O = 0; O < KW; ++O) {
-                const float np = (float)(x ? gep[O + 1] - gep[O + 2] : gep[O] - gep[O + 1]);
-                const float nn = (float)(x ? gen[O] - gen[O + 1] : gen[O + 1] - gen[O + 2]);
-                const float g_lo = my_gt[(O * J + j) * 64 + lane];
-                const float g_hi = my_gt[((O + 1) * J + j) * 64 + lane];
-                const float gp = x ? g_hi : g_lo;
-                const float gn = x ? g_lo : g_hi;
-                u = fmaf(np, gp, u);
-                u = fmaf(-nn, gn, u);
+            for (int r = 0; r <= KW; ++r) {
+                const uint32_t p_ge = r == 0 ? dp : cnt[0][r - 1][j], p_gt = r < KW ? cnt[0][r][j] : 0u;
+                const uint32_t n_ge = r == 0 ? dn : cnt[1][r - 1][j], n_gt = r < KW ? cnt[1][r][j] : 0u;
+                const int32_t d = (int32_t)(p_ge - p_gt) - (int32_t)(n_ge - n_gt);
+                u = fmaf((float)d, my_gt[(r * J + j) * 64 + lane], u);
             }
             U[j] = (double)u;
         }
@@ -1469,6 +1440,9 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
     const uint32_t V = (uint32_t)a.V;
     const int W = a.W;
     const StepScalars c = load_scalars(a, OP);
+    // each wave keeps the dL/dR table of the instance at hand (one table
+    // shared by the block measured slower: the higher occupancy it allows
+    // does not pay)
     __shared__ float s_gt[4][K1 * J * 64];
     __shared__ uint64_t s_win[4][2 * J * 64]; // each wave's transposed record window
     float* my_gt = s_gt[threadIdx.x / 64u];
@@ -1533,7 +1507,7 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
 #pragma unroll
             for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
             double U[J];
-            plane_u<J, KW>(cnt, rm - r0, r1 - rm, oP, my_gt, lane, U);
+            plane_u<J, KW>(cnt, rm - r0, r1 - rm, my_gt, lane, U);
             var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
         }
     }

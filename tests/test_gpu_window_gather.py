@@ -81,6 +81,22 @@ def test_window_gather_long_records(N):
     assert_same(run([cnf], N, 1, 15, params=p), run([cnf], N, 0, 15, params=p))
 
 
+def test_window_gather_off_for_very_frequent_variables():
+    """The window gather keeps per-sign counts in 16 bits; a store with a
+    variable in 2^16 or more clauses of one sign takes the record gather
+    (same results as asking for it)."""
+    rng = np.random.default_rng(21)
+    V, C = 4000, 66000
+    others = rng.choice(np.arange(2, V + 1), size=(C, 2))
+    same = others[:, 0] == others[:, 1]
+    others[same, 1] = others[same, 0] % (V - 1) + 2  # another variable in 2..V
+    sg = rng.choice([-1, 1], size=(C, 2))
+    clauses = [[1, int(a), int(b)] for (a, b) in others * sg]  # variable 1 in every clause
+    cnf = gen.CNF.from_clauses(V, clauses)
+    p = tsat.default_params()
+    assert_same(run([cnf], 64, 1, 6, params=p), run([cnf], 64, 0, 6, params=p))
+
+
 def test_window_gather_batch_with_frozen_instances():
     """Odd instance sizes put chunk boundaries inside instances; the easy
     members freeze on a satisfying candidate while the hard ones go on."""
