@@ -116,6 +116,7 @@ struct VarArgs {
     float* g_out;             // [V][N] or [N][V], may be null
     int32_t g_transposed;
     float beta1, beta2, one_minus_beta1, one_minus_beta2, eps;
+    double inv_n;             // 1 / N (row means and the Eq. 5 backward multiply by it)
     Ctrl* ctrl;
     const InstCtrl* ictrl;    // may be null
     uint8_t* witness;         // [V]

@@ -493,6 +493,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.N = N;
     a.W = W;
     a.Np = Np;
+    a.inv_n = 1.0 / (double)N;
     a.K1 = K1_of(s);
     a.mode = p.norm_mode;
     a.pure_k = s->st.pure_k;

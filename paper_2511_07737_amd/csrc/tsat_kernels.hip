@@ -441,7 +441,10 @@ __device__ __forceinline__ void write_bits(const VarArgs& a, uint32_t v, uint32_
     }
 }
 
-// Row loads of theta (and the optimizer moments for the step).
+// Row loads of theta (and the optimizer moments for the step).  The θ, m, v
+// streams are touched once per iteration, so they go non-temporal: they
+// then do not push the clause planes and literal rows, which the gathers
+// read at random, out of the last-level cache.
 template <int J, int OP, bool FULL = false>
 __device__ __forceinline__ void load_row(const VarArgs& a, uint32_t v, uint32_t lane, float (&th)[J], float (&mm)[J],
                                          float (&vv)[J], bool (&valid)[J])
@@ -451,9 +454,9 @@ __device__ __forceinline__ void load_row(const VarArgs& a, uint32_t v, uint32_t 
         const int i = 64 * j + (int)lane;
         valid[j] = FULL || i < a.N; // FULL: N == 64 J, every lane holds a candidate
         const size_t idx = (size_t)v * a.N + i;
-        th[j] = (OP != OP_ADJ && valid[j]) ? a.theta[idx] : 0.f;
-        mm[j] = (OP == OP_STEP && valid[j]) ? a.m[idx] : 0.f;
-        vv[j] = (OP == OP_STEP && valid[j]) ? a.v[idx] : 0.f;
+        th[j] = (OP != OP_ADJ && valid[j]) ? __builtin_nontemporal_load(a.theta + idx) : 0.f;
+        mm[j] = (OP == OP_STEP && valid[j]) ? __builtin_nontemporal_load(a.m + idx) : 0.f;
+        vv[j] = (OP == OP_STEP && valid[j]) ? __builtin_nontemporal_load(a.v + idx) : 0.f;
     }
 }
 
@@ -482,7 +485,7 @@ __device__ __forceinline__ void var_tail(const VarArgs& a, const StepScalars& c,
         for (int j = 0; j < J; ++j) ut += U[j] * (double)th[j];
         ut = wave_sum(ut);
         const double inv_mu = 1.0 / mu;
-        const double corr = clamped ? 0.0 : ut * inv_mu * inv_mu / (double)N;
+        const double corr = clamped ? 0.0 : ut * inv_mu * inv_mu * a.inv_n;
 #pragma unroll
         for (int j = 0; j < J; ++j) g[j] = (float)(U[j] * inv_mu - corr);
     } else {
@@ -515,16 +518,16 @@ __device__ __forceinline__ void var_tail(const VarArgs& a, const StepScalars& c,
         th[j] = valid[j] ? t : 0.f;
         if (valid[j]) {
             if (!(__builtin_isfinite(t) && __builtin_isfinite(mm) && __builtin_isfinite(vv))) bad = 1;
-            a.theta[idx] = t;
-            a.m[idx] = mm;
-            a.v[idx] = vv;
+            __builtin_nontemporal_store(t, a.theta + idx); // non-temporal: see load_row
+            __builtin_nontemporal_store(mm, a.m + idx);
+            __builtin_nontemporal_store(vv, a.v + idx);
         }
         s2 += (double)th[j];
     }
     if (witness && lane == 0) a.witness[v] = (uint8_t)((oP[wcand >> 6] >> (wcand & 63)) & 1u);
     bool pos = true;
     if (a.mode == 1) {
-        const double mu2 = wave_sum(s2) / (double)N;
+        const double mu2 = wave_sum(s2) * a.inv_n;
         if (lane == 0) a.mu_next[v] = mu2;
         pos = mu2 >= 0.0; // the clamp maps a zero mean to +1e-12
     }
