@@ -83,7 +83,7 @@ def algorithmic_bytes_fwd(cnf, N, planes):
 
 
 KERNEL_SOURCES = ["paper_2511_07737_amd/csrc/tsat_kernels.hip", "paper_2511_07737_amd/csrc/tsat_device.h"]
-PROFILE_FILES = {"large": "profiles/var_plane_kernel__planted-3sat_V1e6_C4.1e6_N256.txt",
+PROFILE_FILES = {"large": "profiles/var_window_kernel__planted-3sat_V1e6_C4.1e6_N256.txt",
                  "structured": "profiles/var_kernel__structured_V5e5_C2.5e6_N128.txt"}
 
 
