@@ -819,16 +819,6 @@ __global__ __launch_bounds__(256) void var_heavy_tail_kernel(VarArgs a)
     if (OP == OP_STEP && ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
 }
 
-// Every clause has the same width k = KO + 1 (KO other literals per record,
-// no header).  Occurrences are taken G records at a time: all their literal
-// rows are requested through the scalar cache before the first wait (the
-// buffers are padded, so the loads need no guards; records past the end of
-// the variable are masked out).  Per candidate and sign, integer counters
-// c_o = #{occurrences whose other literals hold >= o true ones}
-// (o = 1..KO) are accumulated from bit-sliced cumulative masks; then
-// n_O = c_O - c_{O+1} (c_0 = degree) and
-// U = sum_O n+_O g[x + O] - sum_O n-_O g[1 - x + O], x the candidate's own
-// value.  The dL/dR table of the lane's candidates sits in registers.
 // ---------------------------------------------------------------------------
 // Batched scalar-memory gathers.  Scalar loads return out of order, so a
 // wave can only wait for all of its outstanding ones at once; the gather of
@@ -933,6 +923,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     var_pure_body<J, KO, G, OP, FULL>(a);
 }
 
+// Row-gather update for uniform widths: every clause has the same width
+// k = KO + 1 (KO other literals per record, no header).  Occurrences are
+// taken G records at a time: all their literal rows are requested through
+// the scalar cache before the first wait (the buffers are padded, so the
+// loads need no guards; records past the end of the variable are masked
+// out).  Per candidate and sign, integer counters c_o = #{occurrences whose
+// other literals hold >= o true ones} (o = 1..KO) are accumulated from
+// bit-sliced cumulative masks; n_O = c_O - c_{O+1} (c_0 = degree) counts the
+// occurrences with exactly O other literals true, so a positive one has
+// R = x + O and a negative one R = 1 - x + O (x the candidate's own value),
+// and U = sum over r of (positive - negative occurrences with R = r) g[r].
 template <int J, int KO, int G, int OP, bool FULL>
 __device__ __forceinline__ void var_pure_body(const VarArgs& a)
 {
