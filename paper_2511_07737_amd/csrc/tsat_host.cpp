@@ -347,8 +347,19 @@ struct FwdGeom {
 static FwdGeom fwd_geometry(int32_t N, int32_t K1, int64_t Cb, int32_t KW, int32_t target_blocks)
 {
     FwdGeom g;
-    const int bins = (KW <= 4) ? KW + 1 : K1;
     g.Dn = (N + 31) / 32;
+    if (KW > 4) {
+        // wide clauses: blocks of four waves, each wave a run of CPT clauses
+        // for 64 candidates; about four waves per targeted block in all
+        g.DT = 2;
+        g.S = 4;
+        g.tiles = (N + 63) / 64;
+        const int64_t waves = 4 * (int64_t)std::max(1, target_blocks);
+        const int64_t cpt = (Cb * g.tiles + waves - 1) / waves;
+        g.CPT = (int)std::max<int64_t>(8, std::min<int64_t>(1024, cpt));
+        return g;
+    }
+    const int bins = KW + 1;
     g.DT = std::min(g.Dn, 64);
     while (g.DT > 1 && (size_t)g.DT * 32 * bins * 4 > 64 * 1024) g.DT >>= 1;
     g.S = 256 / g.DT;

@@ -191,54 +191,60 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
     }
 }
 
-// Wide clauses (k > 4): bit-sliced 6-plane sum of the literals, then one LDS
-// increment per candidate.
-__global__ __launch_bounds__(256) void fwd_hist_wide_kernel(FwdArgs a)
+// Wide clauses (k > 4): one lane per candidate.  A wave takes a run of
+// consecutive clauses of the bucket (their literal indices come through the
+// scalar cache), reads for each literal the dword of the row that holds its
+// lane's candidate, counts R = the candidate's true literals and adds one to
+// the lane's own LDS bin R (no two lanes share a bin, so no conflicts); the
+// block then adds its four waves' bins into the global histogram.  Clauses
+// are taken G at a time, all their row loads issued before the first wait.
+template <int KMAX, int G>
+__global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
 {
-    extern __shared__ uint32_t lh[]; // [DT*32][K1]
+    extern __shared__ uint32_t lh[]; // [4 waves][64 lanes][K1]
     if (a.ctrl && a.ctrl->stop) return;
     const FwdUnit u = a.units[blockIdx.x];
     if (a.ictrl && a.ictrl[u.inst].frozen) return;
     uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
-    const int tid = threadIdx.x;
-    const int DT = a.DT;
-    const int dl = tid % DT, slot = tid / DT, S = blockDim.x / DT;
-    const int d = blockIdx.y * DT + dl;
-    const int K1 = a.K1;
-    const int nb = DT * 32 * K1;
-    for (int q = tid; q < nb; q += blockDim.x) lh[q] = 0;
-    __syncthreads();
-    if (d < a.Dn && slot < S) {
-        const int64_t c0 = u.c0 + slot;
-        for (int it = 0; it < a.CPT; ++it) {
-            const int64_t c = c0 + (int64_t)it * S;
-            if (c >= u.c1) break;
-            uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
-            for (int q = 0; q < a.KW; ++q) {
-                const uint32_t code = a.codes[c * a.KW + q];
-                uint32_t carry = a.bits32[(size_t)code * a.W2 + d];
+    const uint32_t lane = __lane_id(), wave = threadIdx.x / 64u;
+    const int K1 = a.K1, k = a.KW;
+    const uint32_t cand = blockIdx.y * 64u + lane;
+    const uint32_t d = cand >> 5, bit = cand & 31u;
+    const bool live = (int)d < a.Dn;
+    uint32_t* my = lh + (wave * 64u + lane) * (uint32_t)K1;
+    for (int r = 0; r < K1; ++r) my[r] = 0;
+    // this wave's clauses: CPT consecutive ones of the unit
+    const int64_t cb = u.c0 + (int64_t)wave * a.CPT;
+    const int64_t ce = cb + a.CPT < u.c1 ? cb + a.CPT : u.c1;
+    for (int64_t c = cb; c < ce; c += G) { // wave-uniform
+        uint32_t x[G][KMAX];
 #pragma unroll
-                for (int b = 0; b < 6; ++b) {
-                    const uint32_t t = pl[b] & carry;
-                    pl[b] ^= carry;
-                    carry = t;
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q) {
+                x[g][q] = 0u;
+                if (q < k && c + g < ce) {
+                    const uint32_t code = sload(a.codes + (c + g) * k + q);
+                    if (live) x[g][q] = a.bits32[(size_t)code * a.W2 + d];
                 }
             }
-            for (int p = 0; p < 32; ++p) {
-                uint32_t r = 0;
 #pragma unroll
-                for (int b = 0; b < 6; ++b) r |= ((pl[b] >> p) & 1u) << b;
-                atomicAdd(&lh[(dl * 32 + p) * K1 + r], 1u);
-            }
+        for (int g = 0; g < G; ++g) {
+            if (c + g >= ce) break;
+            uint32_t R = 0;
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q) R += (x[g][q] >> bit) & 1u;
+            if (live) atomicAdd(&my[R], 1u);
         }
     }
     __syncthreads();
-    for (int q = tid; q < nb; q += blockDim.x) {
-        const uint32_t val = lh[q];
-        if (!val) continue;
-        const int cl = q / K1;
-        const int dd = blockIdx.y * DT + cl / 32;
-        if (dd < a.Dn) atomicAdd(&H[(size_t)(blockIdx.y * DT * 32 + cl) * K1 + (q % K1)], val);
+    for (int e = threadIdx.x; e < 64 * K1; e += 256) {
+        const int l = e / K1, r = e % K1;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sum += lh[(w * 64 + l) * K1 + r];
+        const uint32_t cc = blockIdx.y * 64u + (uint32_t)l;
+        if (sum && (int)(cc >> 5) < a.Dn) atomicAdd(&H[(size_t)cc * K1 + r], sum);
     }
 }
 
@@ -1819,8 +1825,10 @@ hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st)
     case 3: return launch_fwd_k<3, 8>(a, grid, st);
     case 4: return launch_fwd_k<4, 8>(a, grid, st);
     default: {
-        const size_t lds = (size_t)a.DT * 32 * a.K1 * sizeof(uint32_t);
-        hipLaunchKernelGGL(fwd_hist_wide_kernel, grid, dim3(256), lds, st, a);
+        const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
+        if (a.KW <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4>), grid, dim3(256), lds, st, a);
+        else if (a.KW <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1>), grid, dim3(256), lds, st, a);
         return hipGetLastError();
     }
     }

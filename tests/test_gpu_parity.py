@@ -108,6 +108,27 @@ def test_mixed_widths_and_edge_clauses(solver):
     one_step_parity(solver, mixed_edge_cnf(), 130, 31, 12)
 
 
+def very_wide_cnf():
+    """Clauses of every width 5..32 (the widest the store takes), so each
+    width class of the wide-clause forward runs, next to some 3-clauses."""
+    rng = np.random.default_rng(17)
+    V = 400
+    clauses = []
+    for k in range(5, 33):
+        for _ in range(40):
+            vs = rng.choice(V, size=k, replace=False) + 1
+            clauses.append([int(x) for x in vs * rng.choice([-1, 1], size=k)])
+    for _ in range(600):
+        vs = rng.choice(V, size=3, replace=False) + 1
+        clauses.append([int(x) for x in vs * rng.choice([-1, 1], size=3)])
+    return gen.CNF.from_clauses(V, clauses)
+
+
+@pytest.mark.parametrize("N", [100, 32])
+def test_very_wide_clauses(solver, N):
+    one_step_parity(solver, very_wide_cnf(), N, 41, 3)
+
+
 def heavy_cnf():
     """Mixed widths where two variables occur in thousands of clauses: their
     occurrence records are split into chunks summed by separate waves."""
