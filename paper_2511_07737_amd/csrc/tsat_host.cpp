@@ -138,6 +138,34 @@ static int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_
     st.inst_off.assign(TSAT_MAX_WIDTH + 1, std::vector<int64_t>((size_t)n_inst + 1, 0));
     for (int k = 0; k <= TSAT_MAX_WIDTH; ++k)
         for (int32_t j = 0; j < n_inst; ++j) st.inst_off[k][j + 1] = st.inst_off[k][j] + inst_cnt[k][j];
+    // Within each instance and width, clauses in lexicographic order of their
+    // (sorted) literal codes: a clause then sits next to the other clauses of
+    // its smallest variable, so the forward's row gathers and the update's
+    // plane gathers of neighbouring variables share cache lines.  The order
+    // is internal: histograms and counts do not depend on it.
+    try {
+        std::vector<int64_t> idx;
+        std::vector<uint32_t> tmp;
+        for (int k = 2; k <= TSAT_MAX_WIDTH; ++k) {
+            auto& b = st.buckets[k];
+            for (int32_t j = 0; j < n_inst; ++j) {
+                const int64_t c0 = st.inst_off[k][j], c1 = st.inst_off[k][j + 1];
+                if (c1 - c0 < 2) continue;
+                idx.resize((size_t)(c1 - c0));
+                for (int64_t c = c0; c < c1; ++c) idx[(size_t)(c - c0)] = c;
+                const uint32_t* base = b.data();
+                std::sort(idx.begin(), idx.end(), [base, k](int64_t x, int64_t y) {
+                    return std::lexicographical_compare(base + x * k, base + x * k + k, base + y * k, base + y * k + k);
+                });
+                tmp.resize((size_t)(c1 - c0) * k);
+                for (size_t q = 0; q < idx.size(); ++q)
+                    std::copy(base + idx[q] * k, base + idx[q] * k + k, tmp.begin() + (ptrdiff_t)(q * k));
+                std::copy(tmp.begin(), tmp.end(), b.begin() + c0 * k);
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(TSAT_E_OOM, "host allocation failed while ordering the clause store");
+    }
     if (!with_occ) return TSAT_OK;
     // per variable: records of positive occurrences, then negative ones;
     // record = (k-1, codes of the other k-1 literals), without the leading
