@@ -79,15 +79,33 @@ __device__ __forceinline__ double readlane_f64(double x, int lane)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ double wave_sum(double x)
+// Sum within each row of 16 lanes (every lane of the row gets it).
+__device__ __forceinline__ double row16_sum(double x)
 {
     x += dpp_f64<0xB1>(x);  // quad_perm [1,0,3,2]
     x += dpp_f64<0x4E>(x);  // quad_perm [2,3,0,1]
     x += dpp_f64<0x124>(x); // row_ror:4
     x += dpp_f64<0x128>(x); // row_ror:8
+    return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x = row16_sum(x);
     const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
     const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
     return (r0 + r1) + (r2 + r3);
+}
+
+// Sum over each half wave (lanes 0-31, 32-63), returned to the lanes of that
+// half.  A half holding a row of at most 32 values gets the wave_sum value
+// of that row alone (there, the other half adds only zeros).
+__device__ __forceinline__ double half_sum(double x)
+{
+    x = row16_sum(x);
+    const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+    const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+    return (__lane_id() < 32u) ? r0 + r1 : r2 + r3;
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
@@ -1528,6 +1546,193 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Window gather with two variables per wave (N <= 32, rows of one word):
+// lanes 0-31 hold the candidates of the first variable of a pair, lanes
+// 32-63 those of the second.  The pair's records are consecutive, so one
+// window loop covers both; every lane reads the transposed word of its
+// candidate (lane mod 32) and counts under its own variable's record masks.
+// The per-variable work of the tail (two FP64 row sums, the divisions,
+// scalar loads, bit packing) is then shared by two rows.  Row sums stay
+// within each half in the order of var_tail, where the idle half adds only
+// zeros, so the results are those of var_window_kernel.
+// ---------------------------------------------------------------------------
+
+// var_tail<1, OP> for two rows, one per half wave (vl: this lane's variable,
+// l: its candidate, live: the lane's variable is present and not frozen).
+template <int OP>
+__device__ __forceinline__ void pair_tail(const VarArgs& a, const StepScalars& c, uint32_t lane, uint32_t vl, uint32_t l,
+                                          bool live, float th, float mm0, float vv0, bool valid, double mu,
+                                          bool clamped, double U, uint64_t own, int witness, int wcand, int& bad)
+{
+    const size_t idx = (size_t)vl * a.N + l;
+    if (OP == OP_ADJ || OP == OP_GRAD) {
+        if (a.U_out && valid) a.U_out[idx] = (float)U;
+        if (OP == OP_ADJ) return;
+    }
+    float g;
+    if (a.mode == 1) {
+        double ut = 0.0;
+        ut += U * (double)th;
+        ut = half_sum(ut);
+        const double inv_mu = 1.0 / mu;
+        const double corr = clamped ? 0.0 : ut * inv_mu * inv_mu * a.inv_n;
+        g = (float)(U * inv_mu - corr);
+    } else {
+        g = (float)U;
+    }
+    if (OP == OP_GRAD) {
+        if (a.g_out && valid) {
+            if (a.g_transposed) a.g_out[(size_t)l * a.V + vl] = g;
+            else a.g_out[idx] = g;
+        }
+        return;
+    }
+    float t = th * c.f_decay;
+    const float mm = c.b1 * mm0 + c.omb1 * g;
+    const float vv = c.b2 * vv0 + c.omb2 * (g * g);
+    const float denom = __builtin_amdgcn_sqrtf(vv) * c.f_isbc2 + c.eps;
+    t = t - c.f_step * (mm * __builtin_amdgcn_rcpf(denom));
+    th = valid ? t : 0.f;
+    if (valid) {
+        if (!(__builtin_isfinite(t) && __builtin_isfinite(mm) && __builtin_isfinite(vv))) bad = 1;
+        __builtin_nontemporal_store(t, a.theta + idx);
+        __builtin_nontemporal_store(mm, a.m + idx);
+        __builtin_nontemporal_store(vv, a.v + idx);
+    }
+    double s2 = 0.0;
+    s2 += (double)th;
+    if (witness && l == 0 && live) a.witness[vl] = (uint8_t)((own >> wcand) & 1u);
+    bool pos = true;
+    if (a.mode == 1) {
+        const double mu2 = half_sum(s2) * a.inv_n;
+        if (l == 0 && live) a.mu_next[vl] = mu2;
+        pos = mu2 >= 0.0; // the clamp maps a zero mean to +1e-12
+    }
+    const uint64_t bal = ballot64(valid && (pos ? th > 0.f : th < 0.f));
+    const uint64_t vm = ballot64(valid);
+    if (l == 0 && live) {
+        const uint32_t sh = lane & 32u;
+        const uint64_t bp = (bal >> sh) & 0xffffffffull, bm = (vm >> sh) & 0xffffffffull;
+        a.lits_next[2 * (size_t)vl] = bp;
+        a.lits_next[2 * (size_t)vl + 1] = ~bp & bm;
+    }
+}
+
+// records of [lo, hi) inside [q, qe) as bits of the window at w (0 if none)
+__device__ __forceinline__ uint64_t window_bits(uint32_t lo, uint32_t hi, uint32_t q, uint32_t qe, uint32_t w)
+{
+    const uint32_t b = lo > q ? lo : q, e = hi < qe ? hi : qe;
+    return b < e ? bit_range(b - w, e - w) : 0ull;
+}
+
+template <int KW, int OP>
+__global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) {
+        copy_bits_on_stop(a);
+        return;
+    }
+    constexpr int K1 = KW + 1;
+    constexpr uint32_t kChunk = 4; // variables (two pairs) per wave work item
+    const uint32_t lane = __lane_id();
+    const uint32_t h = lane >> 5, l = lane & 31u;
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const uint32_t V = (uint32_t)a.V;
+    const int N = a.N, Np = a.Np;
+    const StepScalars c = load_scalars(a, OP);
+    __shared__ float s_gt[4][K1 * 64];
+    __shared__ uint64_t s_win[4][2 * 64];
+    float* my_gt = s_gt[threadIdx.x / 64u];
+    uint64_t* my_win = s_win[threadIdx.x / 64u];
+    uint32_t gt_inst0 = 0xffffffffu, gt_inst1 = 0xffffffffu;
+    int bad = 0;
+    const uint32_t nchunks = (V + kChunk - 1) / kChunk;
+
+    for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
+        const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
+        const uint32_t rend = sload(a.occ_off + ve);
+        uint32_t w = 0;
+        bool loaded = false;
+        for (uint32_t v0 = vb; v0 < ve; v0 += 2) {
+            const uint32_t v1 = v0 + 1;
+            const bool has1 = v1 < ve; // wave-uniform
+            const VarInst i0 = var_instance<OP>(a, v0);
+            VarInst i1 = i0;
+            if (has1) i1 = var_instance<OP>(a, v1);
+            const bool live0 = !i0.frozen, live1 = has1 && !i1.frozen;
+            const uint32_t vl = v0 + h;
+            const bool present = h ? has1 : true, live = h ? live1 : live0;
+            if (present && !live) { // a frozen variable keeps its bits and row mean
+                if (l < 2u) a.lits_next[2 * (size_t)vl + l] = a.lits_cur[2 * (size_t)vl + l];
+                if (l == 0u) a.mu_next[vl] = a.mu_cur[vl];
+            }
+            if (!live0 && !live1) continue;
+            if (i0.inst != gt_inst0 || i1.inst != gt_inst1) {
+                gt_inst0 = i0.inst;
+                gt_inst1 = i1.inst;
+                const float* tg = a.tbl + (size_t)(h ? i1.inst : i0.inst) * K1 * Np;
+#pragma unroll
+                for (int r = 0; r < K1; ++r) my_gt[r * 64 + lane] = tg[(size_t)r * Np + l];
+            }
+            const uint32_t a0 = sload(a.occ_off + v0), am = sload(a.occ_mid + v0), a1 = sload(a.occ_off + v1);
+            uint32_t bm = a1, b1 = a1;
+            if (has1) {
+                bm = sload(a.occ_mid + v1);
+                b1 = sload(a.occ_off + v1 + 1);
+            }
+            // a frozen variable's records are skipped by empty masks
+            const uint32_t pa0 = live0 ? a0 : a1, pam = live0 ? am : a1, pa1 = a1;
+            const uint32_t pb0 = live1 ? a1 : b1, pbm = live1 ? bm : b1, pb1 = b1;
+            uint32_t cnt[KW][1];
+#pragma unroll
+            for (int r = 0; r < KW; ++r) cnt[r][0] = 0;
+            for (uint32_t q = a0; q < b1;) { // wave-uniform
+                if (!loaded || q - w >= 64u) {
+                    w = q;
+                    loaded = true;
+                    load_window<1>(a, w, rend, lane, my_win);
+                }
+                const uint32_t qe = b1 < w + 64u ? b1 : w + 64u;
+                const uint64_t mpa = window_bits(pa0, pam, q, qe, w), mna = window_bits(pam, pa1, q, qe, w);
+                const uint64_t mpb = window_bits(pb0, pbm, q, qe, w), mnb = window_bits(pbm, pb1, q, qe, w);
+                const uint64_t mp = h ? mpb : mpa, mn = h ? mnb : mna;
+                const uint64_t b0 = my_win[l], bb1 = my_win[64 + l];
+                const uint64_t b01 = b0 | bb1; // R >= 1 (bb1: R >= 2)
+                cnt[0][0] += (uint32_t)__popcll(b01 & mp) + ((uint32_t)__popcll(b01 & mn) << 16);
+                cnt[1][0] += (uint32_t)__popcll(bb1 & mp) + ((uint32_t)__popcll(bb1 & mn) << 16);
+                if constexpr (KW == 3) {
+                    const uint64_t b3 = b0 & bb1;
+                    cnt[2][0] += (uint32_t)__popcll(b3 & mp) + ((uint32_t)__popcll(b3 & mn) << 16);
+                }
+                q = qe;
+            }
+            const bool valid = live && (int)l < N;
+            const size_t idx = (size_t)vl * N + l;
+            const float th = (OP != OP_ADJ && valid) ? __builtin_nontemporal_load(a.theta + idx) : 0.f;
+            const float mm0 = (OP == OP_STEP && valid) ? __builtin_nontemporal_load(a.m + idx) : 0.f;
+            const float vv0 = (OP == OP_STEP && valid) ? __builtin_nontemporal_load(a.v + idx) : 0.f;
+            bool c0 = false, c1 = false;
+            double mu0 = 1.0, mu1 = 1.0;
+            if (OP != OP_ADJ && a.mode == 1) {
+                mu0 = clamp_mu(sload(a.mu_cur + v0), c0);
+                if (has1) mu1 = clamp_mu(sload(a.mu_cur + v1), c1);
+            }
+            const uint64_t o0 = sload(a.lits_cur + 2 * (size_t)v0);
+            const uint64_t o1 = has1 ? sload(a.lits_cur + 2 * (size_t)v1) : 0ull;
+            double U[1];
+            plane_u<1, KW>(cnt, h ? bm - a1 : am - a0, h ? b1 - bm : a1 - am, my_gt, lane, U);
+            pair_tail<OP>(a, c, lane, vl, l, live, th, mm0, vv0, valid, h ? mu1 : mu0, h ? c1 : c0, U[0],
+                          h ? o1 : o0, h ? i1.witness : i0.witness, h ? i1.wcand : i0.wcand, bad);
+        }
+    }
+    if (OP == OP_STEP) {
+        if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
+        advance_step(a);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
 
@@ -1958,9 +2163,24 @@ static auto plane_kernel_ptr(bool window)
     return window ? &var_window_kernel<J, KW, OP, FULL> : &var_plane_kernel<J, KW, OP, FULL>;
 }
 
+template <int KW>
+static hipError_t launch_pair_k(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    switch (op) {
+    case OP_STEP: hipLaunchKernelGGL((var_window_pair_kernel<KW, OP_STEP>), dim3(blocks), dim3(256), 0, st, a); break;
+    case OP_GRAD: hipLaunchKernelGGL((var_window_pair_kernel<KW, OP_GRAD>), dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((var_window_pair_kernel<KW, OP_ADJ>), dim3(blocks), dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+// two variables per wave: window gather, rows of at most 32 candidates
+static bool pair_rows(const VarArgs& a) { return a.window && a.N <= 32; }
+
 template <int J, int KW, bool FULL>
 static hipError_t launch_plane_jkf(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
+    if (J == 1 && pair_rows(a)) return launch_pair_k<KW>(a, op, blocks, st);
     const bool win = a.window != 0;
     switch (op) {
     case OP_STEP: hipLaunchKernelGGL((plane_kernel_ptr<J, KW, OP_STEP, FULL>(win)), dim3(blocks), dim3(256), 0, st, a); break;
@@ -2025,6 +2245,8 @@ int var_occupancy(const VarArgs& a, int op)
 {
     if (a.occ_cid && a.planes && op != OP_BINARIZE && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
         const bool k2 = a.pure_k == 2, win = a.window != 0;
+        if (pair_rows(a))
+            return k2 ? occupancy_of(var_window_pair_kernel<2, OP_STEP>, 0) : occupancy_of(var_window_pair_kernel<3, OP_STEP>, 0);
         switch (a.W) {
         case 1: return occupancy_of(k2 ? plane_kernel_ptr<1, 2, OP_STEP, false>(win) : plane_kernel_ptr<1, 3, OP_STEP, false>(win), 0);
         case 2: return occupancy_of(k2 ? plane_kernel_ptr<2, 2, OP_STEP, false>(win) : plane_kernel_ptr<2, 3, OP_STEP, false>(win), 0);
