@@ -439,8 +439,10 @@ typedef struct {
                                   occurrence), 0 = the update gathers the other literals' rows */
     int32_t window_gather;     /* with clause planes: 1 = the update loads the planes of 64 consecutive
                                   occurrence records per vector load and transposes their bits across
-                                  the wavefront, 0 = record by record through the scalar cache;
-                                  default 1 */
+                                  the wavefront (up to 32 candidates: two variables per wavefront),
+                                  0 = record by record through the scalar cache; default 1.  A store
+                                  with a variable in 2^16 or more clauses of one sign always takes
+                                  the record-by-record gather */
     double fwd_ms;             /* tsat_autotune output: forward time per iteration of the choice */
     double var_ms;             /* tsat_autotune output: fused update time per iteration of the choice */
 } tsat_launch_config;
