@@ -112,7 +112,9 @@ def measured_traffic(workload):
 def learned_vs_random():
     """Steps / time to all-SAT (and to the 99% hand-off) from the trained
     proposal network's start and from the N(0,1) start, on a held-out planted
-    3-SAT instance V = 100,000, C = 410,000, 128 restarts, same seeds."""
+    3-SAT instance V = 100,000, C = 410,000, 128 restarts, same seeds; and
+    steps to all-SAT per instance on 400 small held-out instances solved as
+    one batch."""
     from paper_2511_07737_amd import learned
 
     if not os.path.exists(learned.DEFAULT_WEIGHTS):
@@ -121,6 +123,9 @@ def learned_vs_random():
     weights, meta = learned.load_weights()
     res = learned.compare(weights, V=100_000, restarts=128, max_steps=3600, seeds=(1, 2, 3))
     res.pop("runs", None)
+    # steps to all-SAT need instances the search solves: a batch of small
+    # held-out instances, per-instance first satisfying iteration
+    res["small_batch"] = learned.compare_batch(weights, count=400, vmin=200, vmax=1000, ratio=4.0)
     res["training"] = {k: meta.get(k) for k in ("instances", "rows", "val_accuracy", "final_loss", "epochs")}
     return res
 

@@ -264,6 +264,46 @@ def compare(weights: np.ndarray, V: int = 100_000, ratio: float = 4.1, restarts:
                 random=summary("random"), learned=summary("learned"), runs=runs)
 
 
+def compare_batch(weights: np.ndarray, count: int = 400, vmin: int = 200, vmax: int = 1000, ratio: float = 4.0,
+                  restarts: int = 32, max_steps: int = 3000, seed: int = 770_000, params=None,
+                  device: int = 0) -> dict:
+    """Steps to all-SAT per instance from the learned and from the random
+    start, on a batch of small held-out planted instances solved together
+    (each freezes on its first satisfying candidate).  Reports the solved
+    counts and, over the instances both arms solve, the median steps to SAT
+    and how often each start is faster."""
+    params = params or solve_params()
+    rng = np.random.default_rng(seed)
+    Vs = np.exp(rng.uniform(np.log(vmin), np.log(vmax), size=count)).astype(int)
+    cnfs = [gen.planted_ksat(int(v), int(round(ratio * v)), 3, seed=seed + j) for j, v in enumerate(Vs)]
+    steps = {}
+    for arm in ("random", "learned"):
+        s = tsat.Solver(device=device, params=params)
+        s.load_batch(cnfs)
+        net = None
+        if arm == "random":
+            s.init_batch(restarts, seed=1)
+        else:
+            net = tsat.Mlp(weights, device=device)
+            s.propose(net, want_host=False)
+            s.init_from_proposal(restarts, seed=1)
+        s.set_graph(True)
+        s.step(max_steps, stop_on_sat=True)
+        steps[arm] = np.array([x["first_sat_step"] for x in s.instance_status()])
+        if net is not None:
+            net.close()
+        s.close()
+    r, l = steps["random"], steps["learned"]
+    both = (r >= 0) & (l >= 0)
+    med = lambda x: float(np.median(x)) if x.size else None  # noqa: E731
+    return dict(workload=f"{count} held-out planted 3-SAT instances, V log-uniform in [{vmin}, {vmax}], "
+                         f"C = {ratio} V, {restarts} restarts, none-mode tau={params.tau}, cap {max_steps} steps",
+                random=dict(solved=int((r >= 0).sum()), median_steps_to_sat=med(r[r >= 0])),
+                learned=dict(solved=int((l >= 0).sum()), median_steps_to_sat=med(l[l >= 0])),
+                both_solved=int(both.sum()), median_steps_both=dict(random=med(r[both]), learned=med(l[both])),
+                learned_faster=int((l[both] < r[both]).sum()), random_faster=int((r[both] < l[both]).sum()))
+
+
 def save_weights(path: str, params: np.ndarray, meta: dict) -> None:
     os.makedirs(os.path.dirname(path), exist_ok=True)
     np.savez(path, params=params.astype(np.float32), meta=np.array(json.dumps(meta)))
