@@ -63,3 +63,15 @@ def test_committed_network_gains_on_a_held_out_instance():
     assert u_learn < 0.4 * u_rand
     # the hand-off (99% satisfied) is reached no later than from the random start
     assert 0 <= c_learn <= c_rand + 5
+
+
+def test_batch_comparison_reports_steps_to_sat():
+    """The small-instance batch comparison: both starts solve some of the
+    held-out instances; the paired counts are consistent."""
+    w, _ = learned.load_weights()
+    res = learned.compare_batch(w, count=24, vmin=150, vmax=300, ratio=3.8, max_steps=1500)
+    for arm in ("random", "learned"):
+        assert 0 < res[arm]["solved"] <= 24
+        assert res[arm]["median_steps_to_sat"] is not None
+    assert res["both_solved"] <= min(res["random"]["solved"], res["learned"]["solved"])
+    assert res["learned_faster"] + res["random_faster"] <= res["both_solved"]
