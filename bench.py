@@ -111,7 +111,8 @@ def measured_traffic(workload):
 
 def learned_vs_random():
     """Steps / time to all-SAT (and to the 99% hand-off) from the trained
-    proposal network's start and from the N(0,1) start, on a held-out planted
+    proposal network's start, from the majority-vote start (Laplace-smoothed
+    positive-occurrence fraction) and from the N(0,1) start, on a held-out planted
     3-SAT instance V = 100,000, C = 410,000, 128 restarts, same seeds; and
     steps to all-SAT per instance on 400 small held-out instances solved as
     one batch."""

@@ -209,12 +209,31 @@ def solve_params():
     return tsat.default_params(norm_mode=tsat.MODE_NONE, tau=2.0)
 
 
+def majority_proposal(cnfs) -> np.ndarray:
+    """Per variable (of the union of the instances, in load order), the
+    Laplace-smoothed fraction of its occurrences that are positive: its most
+    likely value is the majority polarity vote.  The baseline that shows
+    what the network adds beyond the polarity counts among its features."""
+    out = []
+    for c in (cnfs if isinstance(cnfs, (list, tuple)) else [cnfs]):
+        v = np.abs(c.lits) - 1
+        pos = np.bincount(v[c.lits > 0], minlength=c.num_vars)
+        neg = np.bincount(v[c.lits < 0], minlength=c.num_vars)
+        out.append((pos + 1.0) / (pos + neg + 2.0))
+    return np.concatenate(out).astype(np.float32)
+
+
+ARMS = ("random", "majority", "learned")
+
+
 def run_arm(cnf, arm: str, restarts: int, max_steps: int, seed: int, params, weights=None, device: int = 0):
     s = tsat.Solver(device=device, params=params)
     s.load(cnf)
     net = None
     if arm == "random":
         s.init_batch(restarts, seed=seed)
+    elif arm == "majority":
+        s.init_from_proposal(restarts, seed=seed, p_true=majority_proposal(cnf))
     elif arm == "learned":
         net = tsat.Mlp(weights, device=device)
         s.propose(net, want_host=False)
@@ -240,13 +259,14 @@ def run_arm(cnf, arm: str, restarts: int, max_steps: int, seed: int, params, wei
 
 def compare(weights: np.ndarray, V: int = 100_000, ratio: float = 4.1, restarts: int = 128, max_steps: int = 3600,
             seeds=(1, 2, 3), instance_seed: int = 990_001, params=None, device: int = 0) -> dict:
-    """Steps and time to all-SAT from the learned and from the random start on
-    one held-out planted instance (same seeds for both arms)."""
+    """Steps and time to all-SAT from the random, the majority-vote and the
+    learned start on one held-out planted instance (same seeds for every
+    arm)."""
     params = params or solve_params()
     cnf = gen.planted_ksat(V, int(round(ratio * V)), 3, seed=instance_seed)
     runs = []
     for sd in seeds:
-        for arm in ("random", "learned"):
+        for arm in ARMS:
             runs.append(run_arm(cnf, arm, restarts, max_steps, sd, params, weights, device))
             log(json.dumps(runs[-1]))
 
@@ -261,28 +281,30 @@ def compare(weights: np.ndarray, V: int = 100_000, ratio: float = 4.1, restarts:
 
     return dict(workload=f"held-out planted 3-SAT V={V}, C={int(round(ratio * V))}, {restarts} restarts, "
                          f"none-mode tau={params.tau}, cap {max_steps} steps",
-                random=summary("random"), learned=summary("learned"), runs=runs)
+                random=summary("random"), majority=summary("majority"), learned=summary("learned"), runs=runs)
 
 
 def compare_batch(weights: np.ndarray, count: int = 400, vmin: int = 200, vmax: int = 1000, ratio: float = 4.0,
                   restarts: int = 32, max_steps: int = 3000, seed: int = 770_000, params=None,
                   device: int = 0) -> dict:
-    """Steps to all-SAT per instance from the learned and from the random
-    start, on a batch of small held-out planted instances solved together
-    (each freezes on its first satisfying candidate).  Reports the solved
-    counts and, over the instances both arms solve, the median steps to SAT
-    and how often each start is faster."""
+    """Steps to all-SAT per instance from the random, the majority-vote and
+    the learned start, on a batch of small held-out planted instances solved
+    together (each freezes on its first satisfying candidate).  Reports the
+    solved counts and, over the instances the random and the learned start
+    both solve, the median steps to SAT and how often each is faster."""
     params = params or solve_params()
     rng = np.random.default_rng(seed)
     Vs = np.exp(rng.uniform(np.log(vmin), np.log(vmax), size=count)).astype(int)
     cnfs = [gen.planted_ksat(int(v), int(round(ratio * v)), 3, seed=seed + j) for j, v in enumerate(Vs)]
     steps = {}
-    for arm in ("random", "learned"):
+    for arm in ARMS:
         s = tsat.Solver(device=device, params=params)
         s.load_batch(cnfs)
         net = None
         if arm == "random":
             s.init_batch(restarts, seed=1)
+        elif arm == "majority":
+            s.init_from_proposal(restarts, seed=1, p_true=majority_proposal(cnfs))
         else:
             net = tsat.Mlp(weights, device=device)
             s.propose(net, want_host=False)
@@ -299,6 +321,8 @@ def compare_batch(weights: np.ndarray, count: int = 400, vmin: int = 200, vmax: 
     return dict(workload=f"{count} held-out planted 3-SAT instances, V log-uniform in [{vmin}, {vmax}], "
                          f"C = {ratio} V, {restarts} restarts, none-mode tau={params.tau}, cap {max_steps} steps",
                 random=dict(solved=int((r >= 0).sum()), median_steps_to_sat=med(r[r >= 0])),
+                majority=dict(solved=int((steps["majority"] >= 0).sum()),
+                              median_steps_to_sat=med(steps["majority"][steps["majority"] >= 0])),
                 learned=dict(solved=int((l >= 0).sum()), median_steps_to_sat=med(l[l >= 0])),
                 both_solved=int(both.sum()), median_steps_both=dict(random=med(r[both]), learned=med(l[both])),
                 learned_faster=int((l[both] < r[both]).sum()), random_faster=int((r[both] < l[both]).sum()))

@@ -70,7 +70,7 @@ def test_batch_comparison_reports_steps_to_sat():
     held-out instances; the paired counts are consistent."""
     w, _ = learned.load_weights()
     res = learned.compare_batch(w, count=24, vmin=150, vmax=300, ratio=3.8, max_steps=1500)
-    for arm in ("random", "learned"):
+    for arm in ("random", "majority", "learned"):
         assert 0 < res[arm]["solved"] <= 24
         assert res[arm]["median_steps_to_sat"] is not None
     assert res["both_solved"] <= min(res["random"]["solved"], res["learned"]["solved"])
