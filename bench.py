@@ -131,6 +131,40 @@ def learned_vs_random():
     return res
 
 
+def tiny_distribution():
+    """Steps to all-SAT and to the 99% hand-off on the tiny configuration:
+    32 planted 3-SAT instances V = 200, C = 800 (seeds 1..32), N = 64 with
+    N(0,1) starts (seeds 1001..1032), 500 iterations, solved as one batch
+    that freezes each instance on its first satisfying candidate; for the
+    method's default setting (Eq. 5 mean normalization, tau = 1) and for the
+    none-mode setting the learned proposal uses (tau = 2)."""
+    import numpy as np
+
+    from paper_2511_07737_amd import gen, tsat
+
+    cnfs = [gen.planted_ksat(200, 800, 3, seed=j) for j in range(1, 33)]
+    th = np.concatenate([gen.normal_logits(200, 64, 1000 + j) for j in range(1, 33)])
+    out = {"workload": "32 planted 3-SAT instances V=200, C=800, N=64, 500 iterations"}
+    for name, p in (("mean_tau1", tsat.default_params()),
+                    ("none_tau2", tsat.default_params(norm_mode=tsat.MODE_NONE, tau=2.0))):
+        s = tsat.Solver(params=p)
+        s.load_batch(cnfs)
+        s.init_batch(64, init_logits=th)
+        s.set_graph(True)
+        t0 = time.perf_counter()
+        rep = s.step(500, stop_on_sat=True)
+        wall = time.perf_counter() - t0
+        st = s.instance_status()
+        s.close()
+        sat = np.array([x["first_sat_step"] for x in st])
+        conv = np.array([x["first_converged_step"] for x in st])
+        q = lambda x: [float(v) for v in np.percentile(x, [10, 50, 90])] if x.size else None  # noqa: E731
+        out[name] = {"solved": int((sat >= 0).sum()), "steps_to_sat_p10_p50_p90": q(sat[sat >= 0]),
+                     "reached_99": int((conv >= 0).sum()), "steps_to_99_p10_p50_p90": q(conv[conv >= 0]),
+                     "iterations_run": rep.steps_done, "steps_per_s": rep.steps_done / wall}
+    return out
+
+
 def cpu_baseline(cnf, w, n_sample):
     """The FP64 oracle step, single-threaded, on the same instance with
     n_sample of the candidates."""
@@ -160,7 +194,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-learned", action="store_true",
-                    help="skip the learned-versus-random start comparison")
+                    help="skip the solve-quality reports: the learned-versus-random start comparison and the "
+                         "tiny-configuration steps-to-SAT distribution")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, launch one plain device copy kernel of this many MiB (read + write), "
                          "the reference point for scaling hardware byte counters")
@@ -236,7 +271,12 @@ def main():
         "step_kernel_gbs": round(step_bytes / (kms[2] * 1e-3) / 1e9, 1),
         "best_sat_count": rep.best_sat_count,
         "first_sat_step": rep.first_sat_step,
+        # the exact clause check is the forward histogram: bin 0 counts the
+        # unsatisfied clauses of every candidate
+        "check_pairs_per_s": cnf.num_clauses * N / (kms[0] * 1e-3),
     }
+    if not args.no_learned:
+        out["tiny"] = tiny_distribution()
     if not args.no_learned:
         out["learned_vs_random"] = learned_vs_random()
     if args.calib_copy_mib > 0:
