@@ -84,6 +84,24 @@ def test_window_gather_long_records(N):
     assert_same(run([cnf], N, 1, 15, params=p), run([cnf], N, 0, 15, params=p))
 
 
+@pytest.mark.parametrize("N", [64, 20])
+def test_window_gather_variables_without_occurrences(N):
+    """Variables that occur in no clause (empty record ranges, also inside a
+    window and at the ends of a chunk or pair) get U = 0 like in the record
+    gather."""
+    rng = np.random.default_rng(8)
+    V = 300
+    used = np.arange(1, V + 1)
+    used = used[(used % 7 != 0) & (used > 5) & (used < V - 3)]
+    clauses = []
+    for _ in range(900):
+        vs = rng.choice(used, size=3, replace=False)
+        clauses.append([int(x) for x in vs * rng.choice([-1, 1], size=3)])
+    cnf = gen.CNF.from_clauses(V, clauses)
+    p = tsat.default_params()
+    assert_same(run([cnf], N, 1, 12, params=p), run([cnf], N, 0, 12, params=p))
+
+
 def test_window_gather_off_for_very_frequent_variables():
     """The window gather keeps per-sign counts in 16 bits; a store with a
     variable in 2^16 or more clauses of one sign takes the record gather
