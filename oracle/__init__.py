@@ -59,6 +59,12 @@ def lib():
         L.orc_adamw.argtypes = [i64, P, P, P, P, dbl, dbl, dbl, dbl, dbl, i64]
         L.orc_adamw.restype = None
         L.orc_step.argtypes = [P, i32, P, i64, P, P, P, P, P, P, P, P, P]
+        L.orc_step_ex.argtypes = [P, i32, P, i32, i64, i64, P, P, P, P, P, P, P, P, P, P]
+        L.orc_best_candidate.argtypes = [i32, i32, P]
+        L.orc_best_candidate.restype = i32
+        L.orc_mix.argtypes = [i32, i32, P, i32]
+        L.orc_lit_histogram.argtypes = [P, i32, P, P]
+        L.orc_lit_adjoint.argtypes = [P, i32, P, i32, P, P]
         L.orc_relaxed_S.argtypes = [P, i32, P, i32, dbl]
         L.orc_relaxed_S.restype = dbl
         L.orc_relaxed_fd.argtypes = [P, i32, P, i32, i32, dbl, dbl]
@@ -88,7 +94,7 @@ class Params(ct.Structure):
     _fields_ = [
         ("tau", ct.c_double), ("lr0", ct.c_double), ("decay", ct.c_double), ("lr_min", ct.c_double),
         ("beta1", ct.c_double), ("beta2", ct.c_double), ("eps", ct.c_double), ("weight_decay", ct.c_double),
-        ("every", ct.c_int32), ("restart", ct.c_int32), ("mode", ct.c_int32), ("pad", ct.c_int32),
+        ("every", ct.c_int32), ("restart", ct.c_int32), ("mode", ct.c_int32), ("mix", ct.c_int32),
     ]
 
 
@@ -98,7 +104,7 @@ MODE_MEAN = 1
 
 def default_params(**kw) -> Params:
     d = dict(tau=1.0, lr0=0.1, decay=0.1, lr_min=1e-15, beta1=0.9, beta2=0.999, eps=1e-8,
-             weight_decay=1e-2, every=30, restart=360, mode=MODE_MEAN, pad=0)
+             weight_decay=1e-2, every=30, restart=360, mode=MODE_MEAN, mix=0)
     d.update(kw)
     return Params(**d)
 
@@ -215,23 +221,61 @@ def adamw(theta, m, v, g, lr_, t, beta1=0.9, beta2=0.999, eps=1e-8, wd=1e-2):
     lib().orc_adamw(theta.size, _p(theta), _p(m), _p(v), _p(g), float(lr_), beta1, beta2, eps, wd, int(t))
 
 
-def step(cnf: Cnf, theta, m, v, t: int, p: Params | None = None):
-    """One iteration from (theta, m, v) at 0-based index t.  Returns a dict with
-    the new state and the intermediate quantities."""
+def step(cnf: Cnf, theta, m, v, t: int, p: Params | None = None, t_reset: int = 0, literal_rows: bool = False):
+    """One iteration from (theta, m, v) at 0-based index t (orc_step_ex).
+    literal_rows: theta has 2V rows, one per literal (row 2v = x_v, 2v+1 =
+    not x_v).  Returns a dict with the new state, the intermediate
+    quantities and ``mixed`` (the best candidate of a mixing iteration, else -1)."""
     p = p or default_params()
     theta = np.array(theta, dtype=np.float64, order="C", copy=True)
     m = np.array(m, dtype=np.float64, order="C", copy=True)
     v = np.array(v, dtype=np.float64, order="C", copy=True)
-    V, N = theta.shape
-    b = np.empty((V, N), dtype=np.uint8)
+    rows, N = theta.shape
+    b = np.empty((rows, N), dtype=np.uint8)
     H = np.empty((N, cnf.K + 1), dtype=np.int64)
     S = np.empty(N, dtype=np.float64)
-    U = np.empty((V, N), dtype=np.float64)
-    g = np.empty((V, N), dtype=np.float64)
+    U = np.empty((rows, N), dtype=np.float64)
+    g = np.empty((rows, N), dtype=np.float64)
     loss = ct.c_double()
-    _check(lib().orc_step(cnf.handle, N, ct.byref(p), int(t), _p(theta), _p(m), _p(v), _p(b), _p(H),
-                          _p(S), ct.cast(ct.byref(loss), ct.c_void_p), _p(U), _p(g)), "step")
-    return dict(theta=theta, m=m, v=v, bits=b, H=H, S=S, loss=float(loss.value), U=U, g=g)
+    mixed = ct.c_int32(-1)
+    _check(lib().orc_step_ex(cnf.handle, N, ct.byref(p), 2 if literal_rows else 1, int(t), int(t_reset), _p(theta),
+                             _p(m), _p(v), _p(b), _p(H), _p(S), ct.cast(ct.byref(loss), ct.c_void_p), _p(U), _p(g),
+                             ct.cast(ct.byref(mixed), ct.c_void_p)), "step")
+    return dict(theta=theta, m=m, v=v, bits=b, H=H, S=S, loss=float(loss.value), U=U, g=g, mixed=int(mixed.value))
+
+
+def best_candidate(H: np.ndarray) -> int:
+    """Most satisfied clauses (fewest R = 0), the lower index on ties."""
+    H = np.ascontiguousarray(H, dtype=np.int64)
+    N, K1 = H.shape
+    return int(lib().orc_best_candidate(N, K1 - 1, _p(H)))
+
+
+def mix(theta: np.ndarray, istar: int) -> np.ndarray:
+    """Assignment mixing into candidate istar (a new array)."""
+    th = np.array(theta, dtype=np.float64, order="C", copy=True)
+    rows, N = th.shape
+    _check(lib().orc_mix(rows, N, _p(th), int(istar)), "mix")
+    return th
+
+
+def lit_histogram(cnf: Cnf, bl: np.ndarray) -> np.ndarray:
+    """H[N][K+1] of independent literal rows bl [2V][N]."""
+    bl = np.ascontiguousarray(bl, dtype=np.uint8)
+    N = bl.shape[1]
+    H = np.empty((N, cnf.K + 1), dtype=np.int64)
+    _check(lib().orc_lit_histogram(cnf.handle, N, _p(bl), _p(H)), "lit_histogram")
+    return H
+
+
+def lit_adjoint(cnf: Cnf, bl: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """U2[2V][N]: dL/dA of every literal row (straight-through, +1)."""
+    bl = np.ascontiguousarray(bl, dtype=np.uint8)
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    N = bl.shape[1]
+    U2 = np.empty((2 * cnf.V, N), dtype=np.float64)
+    _check(lib().orc_lit_adjoint(cnf.handle, N, _p(bl), table.shape[1] - 1, _p(table), _p(U2)), "lit_adjoint")
+    return U2
 
 
 def relaxed_S(cnf: Cnf, x: np.ndarray, i: int, tau: float = 1.0) -> float:

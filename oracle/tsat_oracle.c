@@ -58,6 +58,24 @@
  *       e = v*N + i and key (seed mod 2^32, seed div 2^32); the N(0,1) draw is
  *       Box-Muller on the first two output words, the Bernoulli draw compares
  *       the third word with floor(p * 2^32).
+ *   R12 Assignment mixing (the paragraph of Sec. IV-A that the source leaves
+ *       commented out, with its equation): it happens at the learning-rate
+ *       restarts, i.e. iterations t > 0 with t mod 360 = 0, after that
+ *       iteration's forward pass; the best candidate i* has the most
+ *       satisfied clauses (lower index on ties); every other candidate's
+ *       real-valued row entries become the average of its own and i*'s;
+ *       "resetting the optimizer" is read as a fresh AdamW: m = v = 0 and
+ *       the bias-correction count restarts at 1 with the next update.  The
+ *       mixing iteration takes no gradient step of its own.  Off unless
+ *       params.mix is set (the published method does not mix).
+ *   R13 Independent literal rows (A_real in R^{2V x N}, Sec. III-B, with the
+ *       incomplete-assignment passage of Sec. III-A that the source leaves
+ *       commented out): each literal has its own row of logits, Eq. 5 and
+ *       Eq. 2 apply per literal row, R counts the literals whose own row is
+ *       1 (a variable with both rows 1 is a "don't care" that satisfies
+ *       every clause holding either literal; both rows 0 satisfy nothing),
+ *       and the straight-through gradient of a literal row is the sum of
+ *       dL/dR over the clauses holding that literal.
  *   R11 Initialisation from a proposal p_v (orc_init_proposal): b ~ Bern(p_v),
  *       theta = +|z| where b = 1 and -|z| where b = 0 (z the N(0,1) draw of
  *       the random initialisation).  In mean mode a row's negative entries are
@@ -390,47 +408,160 @@ void orc_adamw(int64_t n, double *theta, double *m, double *v, const double *g, 
 
 typedef struct {
     double tau, lr0, decay, lr_min, beta1, beta2, eps, weight_decay;
-    int32_t every, restart, mode, pad;
+    int32_t every, restart, mode, mix;
 } orc_params;
 
-/* Given theta, m, v (V x N, updated in place) and the 0-based iteration index
- * t: binarize -> R -> SmoothMin/loss -> dL/dR -> P^T + STE -> Eq. 5 backward
- * -> AdamW with lr(t) and bias-correction count t+1.  Optional outputs (any
- * may be NULL): the bits used by the forward pass, H, S, loss, U and g. */
+/* ------------------------------------------------------------------------ */
+/* Assignment mixing at a learning-rate restart (Sec. IV-A, the paragraph    */
+/* left commented out in the source, and its equation) -- reading R12        */
+/* ------------------------------------------------------------------------ */
+
+/* The best candidate: most satisfied clauses, i.e. fewest clauses with
+ * R = 0 (H[i][0]), the lower index on ties. */
+int32_t orc_best_candidate(int32_t N, int32_t K, const int64_t *H)
+{
+    int32_t best = 0;
+    for (int32_t i = 1; i < N; ++i)
+        if (H[(int64_t)i * (K + 1)] < H[(int64_t)best * (K + 1)]) best = i;
+    return best;
+}
+
+/* Every candidate column i other than istar becomes the average of itself
+ * and column istar, row by row: theta[v][i] <- (theta[v][i] + theta[v][istar]) / 2. */
+int orc_mix(int32_t rows, int32_t N, double *theta, int32_t istar)
+{
+    if (rows < 0 || N <= 0 || !theta || istar < 0 || istar >= N) return ORC_E_ARG;
+    for (int32_t v = 0; v < rows; ++v) {
+        double *row = theta + (int64_t)v * N;
+        double best = row[istar];
+        for (int32_t i = 0; i < N; ++i)
+            if (i != istar) row[i] = 0.5 * (row[i] + best);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Independent literal rows (Sec. III-B: A_real has 2V rows; the            */
+/* incomplete-assignment passage of Sec. III-A left commented out in the    */
+/* source) -- reading R13                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Row of literal x (signed, 1-based) in a [2V][N] literal-row matrix:
+ * x_v is row 2(v-1), not-x_v row 2(v-1)+1. */
+static inline int64_t lit_row(int32_t x) { return x > 0 ? 2 * (int64_t)(x - 1) : 2 * (int64_t)(-x - 1) + 1; }
+
+/* H[i][r] = #{c : R[c][i] = r} with R_ci = sum over the literals l of c of
+ * bl[row(l)][i]: a literal counts when its own row holds 1, whatever the
+ * row of its complement holds (both 1: either literal satisfies its
+ * clauses; both 0: neither does). */
+int orc_lit_histogram(const void *h, int32_t N, const uint8_t *bl, int64_t *H)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !bl || !H) return ORC_E_ARG;
+    int32_t K = f->K;
+    memset(H, 0, sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
+    for (int64_t c = 0; c < f->C; ++c)
+        for (int32_t i = 0; i < N; ++i) {
+            int32_t r = 0;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) r += bl[lit_row(f->lit[q]) * N + i];
+            H[(int64_t)i * (K + 1) + r] += 1;
+        }
+    return ORC_OK;
+}
+
+/* U2[l][i] = dL/dA[l][i] = sum over the clauses c holding literal l of
+ * dL/dR_ci (the transpose product); with independent rows the
+ * straight-through estimator passes it to the literal's own row with +1. */
+int orc_lit_adjoint(const void *h, int32_t N, const uint8_t *bl, int32_t K, const double *table, double *U2)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || N <= 0 || !bl || !table || !U2 || K < f->K) return ORC_E_ARG;
+    memset(U2, 0, sizeof(double) * (size_t)f->V * 2 * (size_t)N);
+    for (int64_t c = 0; c < f->C; ++c)
+        for (int32_t i = 0; i < N; ++i) {
+            int32_t r = 0;
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) r += bl[lit_row(f->lit[q]) * N + i];
+            double dR = table[(int64_t)i * (K + 1) + r];
+            for (int64_t q = f->off[c]; q < f->off[c + 1]; ++q) U2[lit_row(f->lit[q]) * N + i] += dR;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One iteration of the method, in the order of Sec. III-B and IV-A          */
+/* ------------------------------------------------------------------------ */
+
+/* Given theta, m, v (updated in place) and the 0-based iteration index t:
+ * binarize -> R -> SmoothMin/loss -> dL/dR -> P^T + STE -> Eq. 5 backward
+ * -> AdamW with lr(t).  rows_per_var = 1: theta is V x N, one row per
+ * variable (complete assignments, reading R1); 2: theta is 2V x N, one row
+ * per literal (reading R13).  t_reset: the iteration at which the optimizer
+ * state last started from zero (0 for a fresh batch); the bias-correction
+ * count of the update is t - t_reset + 1.
+ * With p->mix, an iteration t > 0 with t mod restart = 0 does not take a
+ * gradient step: after the forward pass it mixes the candidates into the
+ * best one (orc_best_candidate, orc_mix) and resets the optimizer (m = v =
+ * 0; the next update is the first of a fresh AdamW, so the caller passes
+ * t_reset = t + 1 from then on); *mixed_out (may be NULL) receives the best
+ * candidate, else -1.  Optional outputs (any may be NULL): the bits used by
+ * the forward pass, H, S, loss, U and g (zero at a mixing iteration). */
+int orc_step_ex(const void *h, int32_t N, const orc_params *p, int32_t rows_per_var, int64_t t, int64_t t_reset,
+                double *theta, double *m, double *v, uint8_t *b_out, int64_t *H_out, double *S_out,
+                double *loss_out, double *U_out, double *g_out, int32_t *mixed_out)
+{
+    const ocnf *f = (const ocnf *)h;
+    if (!f || !p || N <= 0 || !theta || !m || !v || (rows_per_var != 1 && rows_per_var != 2) || t_reset > t)
+        return ORC_E_ARG;
+    int32_t K = f->K;
+    int32_t rows = rows_per_var * f->V;
+    int64_t RN = (int64_t)rows * N;
+    uint8_t *b = (uint8_t *)malloc((size_t)(RN > 0 ? RN : 1));
+    int64_t *H = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
+    double *S = (double *)malloc(sizeof(double) * (size_t)N);
+    double *table = (double *)malloc(sizeof(double) * (size_t)N * (size_t)(K + 1));
+    double *U = (double *)calloc((size_t)(RN > 0 ? RN : 1), sizeof(double));
+    double *g = (double *)calloc((size_t)(RN > 0 ? RN : 1), sizeof(double));
+    int rc = ORC_E_OOM;
+    if (!b || !H || !S || !table || !U || !g) goto done;
+    double loss = 0.0;
+    rc = orc_binarize(rows, N, theta, p->mode, b, NULL);
+    if (!rc) rc = rows_per_var == 1 ? orc_histogram(h, N, b, H) : orc_lit_histogram(h, N, b, H);
+    if (!rc) rc = orc_smoothmin(N, K, H, p->tau, NULL, S, table, &loss);
+    if (rc) goto done;
+    const int mixing = p->mix && t > 0 && p->restart > 0 && t % p->restart == 0;
+    if (!mixing) {
+        rc = rows_per_var == 1 ? orc_adjoint(h, N, b, K, table, U) : orc_lit_adjoint(h, N, b, K, table, U);
+        if (!rc) rc = orc_norm_backward(rows, N, theta, p->mode, U, g);
+        if (rc) goto done;
+    }
+    if (b_out) memcpy(b_out, b, (size_t)RN);
+    if (H_out) memcpy(H_out, H, sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
+    if (S_out) memcpy(S_out, S, sizeof(double) * (size_t)N);
+    if (loss_out) *loss_out = loss;
+    if (U_out) memcpy(U_out, U, sizeof(double) * (size_t)RN);
+    if (g_out) memcpy(g_out, g, sizeof(double) * (size_t)RN);
+    if (mixing) {
+        int32_t istar = orc_best_candidate(N, K, H);
+        rc = orc_mix(rows, N, theta, istar);
+        for (int64_t j = 0; j < RN; ++j) m[j] = v[j] = 0.0;
+        if (mixed_out) *mixed_out = istar;
+    } else {
+        orc_adamw(RN, theta, m, v, g, orc_lr(t, p->lr0, p->decay, p->every, p->restart, p->lr_min),
+                  p->beta1, p->beta2, p->eps, p->weight_decay, t - t_reset + 1);
+        if (mixed_out) *mixed_out = -1;
+    }
+done:
+    free(b); free(H); free(S); free(table); free(U); free(g);
+    return rc;
+}
+
+/* The iteration of orc_step_ex for complete assignments from a fresh
+ * optimizer (t_reset = 0). */
 int orc_step(const void *h, int32_t N, const orc_params *p, int64_t t, double *theta, double *m,
              double *v, uint8_t *b_out, int64_t *H_out, double *S_out, double *loss_out,
              double *U_out, double *g_out)
 {
-    const ocnf *f = (const ocnf *)h;
-    if (!f || !p || N <= 0 || !theta || !m || !v) return ORC_E_ARG;
-    int32_t V = f->V, K = f->K;
-    int64_t VN = (int64_t)V * N;
-    uint8_t *b = (uint8_t *)malloc((size_t)(VN > 0 ? VN : 1));
-    int64_t *H = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
-    double *S = (double *)malloc(sizeof(double) * (size_t)N);
-    double *table = (double *)malloc(sizeof(double) * (size_t)N * (size_t)(K + 1));
-    double *U = (double *)malloc(sizeof(double) * (size_t)(VN > 0 ? VN : 1));
-    double *g = (double *)malloc(sizeof(double) * (size_t)(VN > 0 ? VN : 1));
-    int rc = ORC_E_OOM;
-    if (!b || !H || !S || !table || !U || !g) goto done;
-    double loss = 0.0;
-    rc = orc_binarize(V, N, theta, p->mode, b, NULL);
-    if (!rc) rc = orc_histogram(h, N, b, H);
-    if (!rc) rc = orc_smoothmin(N, K, H, p->tau, NULL, S, table, &loss);
-    if (!rc) rc = orc_adjoint(h, N, b, K, table, U);
-    if (!rc) rc = orc_norm_backward(V, N, theta, p->mode, U, g);
-    if (rc) goto done;
-    if (b_out) memcpy(b_out, b, (size_t)VN);
-    if (H_out) memcpy(H_out, H, sizeof(int64_t) * (size_t)N * (size_t)(K + 1));
-    if (S_out) memcpy(S_out, S, sizeof(double) * (size_t)N);
-    if (loss_out) *loss_out = loss;
-    if (U_out) memcpy(U_out, U, sizeof(double) * (size_t)VN);
-    if (g_out) memcpy(g_out, g, sizeof(double) * (size_t)VN);
-    orc_adamw(VN, theta, m, v, g, orc_lr(t, p->lr0, p->decay, p->every, p->restart, p->lr_min),
-              p->beta1, p->beta2, p->eps, p->weight_decay, t + 1);
-done:
-    free(b); free(H); free(S); free(table); free(U); free(g);
-    return rc;
+    return orc_step_ex(h, N, p, 1, t, 0, theta, m, v, b_out, H_out, S_out, loss_out, U_out, g_out, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
