@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libtsat.so")
 ARCH = os.environ.get("TSAT_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["tsat_kernels.hip", "tsat_learned.hip"]
-HOST_SOURCES = ["tsat_host.cpp", "tsat_mlp.cpp"]
+HOST_SOURCES = ["tsat_host.cpp", "tsat_mlp.cpp", "tsat_store.cpp"]
 # hipcc's host pass does not know this device feature and warns; harmless.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tsat_types.h"
+
 namespace tsat {
 
 // Solver-wide control block in device memory.  The SmoothMin kernel writes
@@ -43,12 +45,6 @@ struct InstCtrl {
     int32_t sat_cand;        // first satisfying candidate
     int32_t frozen;          // stop_on_sat: no further updates of this instance
     int32_t witness_pending; // the pending update records the satisfying candidate
-};
-
-// Static per-instance sizes.
-struct InstInfo {
-    int64_t C;       // clauses, empty ones included
-    int64_t n_empty; // empty clauses (R = 0 for every candidate)
 };
 
 // One forward work unit: a clause range of one instance inside one bucket.

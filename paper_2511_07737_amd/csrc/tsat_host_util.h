@@ -1,5 +1,5 @@
-// tsat_host_util.h -- error reporting, device buffers and small helpers
-// shared by the host translation units of the library.
+// tsat_host_util.h -- device buffers and small helpers shared by the host
+// translation units of the library that use the HIP runtime.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,22 +10,9 @@
 #include <string>
 
 #include "tsat.h"
+#include "tsat_err.h"
 
 namespace tsat_host {
-
-// the message behind tsat_last_error(): one per host thread
-inline thread_local std::string g_err;
-
-inline int32_t fail(int32_t code, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
 
 // allocation-failure injection for tests of the OOM path: the environment
 // variable TSAT_FAIL_ALLOC_AFTER=n makes the (n+1)-th device allocation fail
@@ -87,10 +74,4 @@ struct DBuf {
     do {                                                                                               \
         hipError_t e_ = (x);                                                                           \
         if (e_ != hipSuccess) return tsat_host::fail(TSAT_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
-    } while (0)
-
-#define RET(x)                       \
-    do {                             \
-        int32_t r_ = (x);            \
-        if (r_ != TSAT_OK) return r_; \
     } while (0)

@@ -1325,7 +1325,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
                 uint64_t w[G][2][J];
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    const uint64_t* pl = (const uint64_t*)(plane_base + id[g] * plane_bytes);
+                    const uint64_t* pl = (const uint64_t*)(plane_base + (size_t)id[g] * plane_bytes);
 #pragma unroll
                     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -1424,8 +1424,9 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane)
 
 // Planes of records [w, w + 64) (records at or past `end` read as zero),
 // transposed into the wave's LDS window: win[(p J + j) 64 + lane] bit r =
-// plane p, word j, candidate bit of record w + r (lane-private slots, so the
-// wave needs no barrier).
+// plane p, word j, candidate bit of record w + r.  Each lane writes its own
+// slots; a caller whose lanes read other lanes' slots (the two-variable
+// gather) orders the stores before those loads itself.
 template <int J>
 __device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane, uint64_t* win)
 {
@@ -1692,6 +1693,11 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
                     w = q;
                     loaded = true;
                     load_window<1>(a, w, rend, lane, my_win);
+                    // lanes 32-63 read the slots lanes 0-31 wrote: order the
+                    // LDS stores before those loads for the compiler and the wave
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
                 const uint32_t qe = b1 < w + 64u ? b1 : w + 64u;
                 const uint64_t mpa = window_bits(pa0, pam, q, qe, w), mna = window_bits(pam, pa1, q, qe, w);

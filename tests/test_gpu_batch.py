@@ -167,3 +167,18 @@ def test_handoff_stop_mode_freezes_at_convergence(solver):
     bits = solver.get_bits()
     solver.step(5, params=p, stop_on_sat=2)
     assert np.array_equal(solver.get_bits(), bits)
+
+
+def test_ragged_witness_check_uses_the_library():
+    """The ragged report verifies witnesses with the library's exact check:
+    a planted assignment holds, its complement and a CNF with an empty clause
+    do not (the expected verdicts come from the generator's planted
+    assignment and a naive clause evaluation here)."""
+    from paper_2511_07737_amd import ragged
+
+    c = gen.planted_ksat(500, 2100, 3, seed=3)
+    assert ragged.witness_holds(c, c.planted)
+    flipped = (1 - c.planted).astype(np.uint8)
+    naive = all(any((flipped[abs(x) - 1] == 1) == (x > 0) for x in c.clause(j)) for j in range(c.num_clauses))
+    assert ragged.witness_holds(c, flipped) == naive
+    assert not ragged.witness_holds(gen.CNF.from_clauses(3, [[1], []]), np.ones(3, np.uint8))

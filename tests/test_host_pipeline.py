@@ -14,14 +14,20 @@ def test_parallel_generation_matches_sequential():
     assert 3.79 <= min(ratios) and max(ratios) <= 4.21
 
 
-def test_host_witness_check():
-    c = gen.planted_ksat(500, 2100, 3, seed=3)
-    assert ragged.satisfies(c, c.planted)
-    flipped = c.planted.copy()
-    flipped[:] = 1 - flipped
-    assert not ragged.satisfies(c, flipped)
-    assert not ragged.satisfies(gen.CNF.from_clauses(3, [[1], []]), np.ones(3, np.uint8))
-    assert ragged.satisfies(gen.CNF.from_clauses(3, []), np.zeros(3, np.uint8))
+def test_censored_percentiles():
+    # 10 instances, 4 solved: the median lies among the censored ones
+    solved = [5.0, 1.0, 3.0, 2.0]
+    assert ragged.censored_percentile(solved, 10, 50) is None
+    assert ragged.censored_percentile(solved, 10, 10) == 1.0  # rank 1
+    assert ragged.censored_percentile(solved, 10, 40) == 5.0  # rank 4
+    assert ragged.censored_percentile(solved, 10, 41) is None  # rank 5
+    # nothing censored: the order statistic of rank ceil(q n / 100)
+    xs = np.arange(100, 0, -1).astype(float)
+    assert ragged.censored_percentile(xs, 100, 50) == 50.0
+    assert ragged.censored_percentile(xs, 100, 99) == 99.0
+    assert ragged.censored_percentile(xs, 100, 100) == 100.0
+    assert ragged.censored_percentile([], 0, 50) is None
+    assert ragged.censored_percentile([], 3, 1) is None
 
 
 def test_column_bits_matches_pack_helpers():
