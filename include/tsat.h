@@ -70,6 +70,14 @@ typedef struct {
     int32_t restart_every;/* iterations per learning-rate restart (> 0) */
     int32_t norm_mode;    /* TSAT_MODE_MEAN or TSAT_MODE_NONE */
     int32_t k_partial;    /* partial-assignment size; <= 0: max(20, ceil(V/1e4)) */
+    int32_t mix;          /* 1: assignment mixing at every learning-rate restart (iterations t > 0 with
+                             t mod restart_every = 0; the paragraph of Sec. IV-A the published text
+                             leaves out, with its equation): after the iteration's forward pass each
+                             candidate i other than the best one i* (most satisfied clauses, lower
+                             index on ties) becomes (theta_i + theta_i*) / 2 per variable, and the
+                             optimizer is reset (m = v = 0, bias corrections counted from the next
+                             iteration); the iteration takes no gradient step.  0 (default): off */
+    int32_t reserved;
 } tsat_params;
 
 typedef struct {
@@ -296,6 +304,15 @@ int32_t tsat_set_state(tsat_solver* s, const float* theta, const float* m, const
 /* Copy the optimizer state out; any pointer may be NULL. */
 int32_t tsat_get_state(tsat_solver* s, float* theta, float* m, float* v, int64_t* t);
 
+/* Iteration at which the AdamW moments last started from zero: 0 after
+ * tsat_init_batch / tsat_set_state, t + 1 after a mixing iteration t
+ * (params.mix).  The update of iteration t uses the bias-correction count
+ * t - origin + 1.  Get and set it to checkpoint and resume a run with
+ * mixing (set it after tsat_set_state; E_ARG if origin > the next
+ * iteration index or < 0). */
+int32_t tsat_get_adam_origin(tsat_solver* s, int64_t* origin);
+int32_t tsat_set_adam_origin(tsat_solver* s, int64_t origin);
+
 /* Current binarized batch, host [V][ceil(N/64)] uint64. */
 int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed);
 
@@ -334,6 +351,48 @@ int32_t tsat_fwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
  * for x_v and -1 for not-x_v.  N <= TSAT_MAX_STEP_N. */
 int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, const float* dS, float* U,
                      void* stream);
+
+/* The differentiable path of Fig. 3 on caller logits theta (device [V][N]
+ * float, the real-valued assignment matrix; N <= TSAT_MAX_STEP_N), for a
+ * single-instance solver; mode is TSAT_MODE_MEAN (Eq. 5 normalization
+ * before Eq. 2) or TSAT_MODE_NONE.  Same stream and scratch rules as above.
+ * E_ARG for NULL required pointers, N or mode out of range, tau < 0;
+ * E_STATE before a CNF is loaded or with more than one instance. */
+
+/* Eq. 5 then Eq. 2 (Sec. IV-A, Sec. III-B): mu_v = (1/N) sum_i theta_vi
+ * (FP64; |mu| < 1e-12 is clamped to +-1e-12, 0 to +1e-12) and
+ * b_vi = B(theta_vi / mu_v) = [theta_vi mu_v > 0] (mean mode) or
+ * [theta_vi > 0] (none).  Outputs, any may be NULL but not all: bits device
+ * [V][ceil(N/64)] uint64 (the literal x_v; not x_v is the complement),
+ * assign device [V][N] float (b as 0.0 / 1.0), mu device [V] double (the
+ * unclamped means; 1.0 in none mode). */
+int32_t tsat_binarize_dev(tsat_solver* s, const float* theta, int32_t N, int32_t mode, uint64_t* bits, float* assign,
+                          double* mu, void* stream);
+
+/* Backward of Eq. 5 (the straight-through estimator passes the gradient
+ * through Eq. 2 unchanged, Sec. III-B): given dA = dLoss/d(theta/mu)
+ * (device [V][N]), writes g = dLoss/dtheta (device [V][N]):
+ * g_vi = dA_vi / mu_v - (sum_k dA_vk theta_vk) / (N mu_v^2) in mean mode
+ * (the second term is dropped where the mean is clamped), g = dA in none
+ * mode.  The row means are recomputed from theta as tsat_binarize_dev forms
+ * them. */
+int32_t tsat_norm_backward_dev(tsat_solver* s, const float* theta, const float* dA, int32_t N, int32_t mode, float* g,
+                               void* stream);
+
+/* Loss of the logits: Eq. 5 -> Eq. 2 -> R = P A (Eq. 1) -> SmoothMin with
+ * temperature tau (Eq. 4) -> loss = -sum_i S_i (Eq. 3).  Outputs: loss
+ * (device float scalar, required; the sum is formed in FP64), S device [N]
+ * float and bits device [V][ceil(N/64)] (both may be NULL). */
+int32_t tsat_loss_dev(tsat_solver* s, const float* theta, int32_t N, float tau, int32_t mode, float* loss, float* S,
+                      uint64_t* bits, void* stream);
+
+/* Gradient of that loss times the upstream scalar dloss (device float,
+ * NULL = 1): g = dloss * dLoss/dtheta (device [V][N], required), through
+ * the transpose product with the straight-through estimator and the Eq. 5
+ * backward in one pass over the variables; U (device [V][N], may be NULL)
+ * receives dloss * dLoss/d(theta/mu). */
+int32_t tsat_loss_backward_dev(tsat_solver* s, const float* theta, int32_t N, float tau, int32_t mode,
+                               const float* dloss, float* g, float* U, void* stream);
 
 /* --------------------------------------------------- learned proposal --- */
 /*

@@ -20,7 +20,7 @@ namespace tsat {
 // host round trip.
 struct Ctrl {
     int64_t t;          // next 0-based iteration index
-    int64_t updates;    // AdamW updates performed (lifetime)
+    int64_t updates;    // iterations performed (lifetime)
     double lr;          // learning rate of the pending update
     int32_t stop;       // every instance is frozen: kernels return at entry
     int32_t stop_on_sat;
@@ -30,6 +30,9 @@ struct Ctrl {
     float f_step;       // lr / (1 - beta1^t)
     float f_isbc2;      // 1 / sqrt(1 - beta2^t)
     float pad0;
+    int64_t t_reset;    // iteration at which the AdamW moments last started from zero
+    int32_t mixing;     // the pending update is an assignment mixing (no gradient step)
+    int32_t pad1;
 };
 
 // Per-instance bookkeeping, written by the SmoothMin kernel.
@@ -79,7 +82,9 @@ struct SminArgs {
     float* S_out;           // [n_inst][N] SmoothMin, may be null
     double* S64_out;        // [n_inst][N] SmoothMin in FP64, may be null
     int64_t* sat_out;       // [n_inst][N] satisfied clauses, may be null
-    const float* dS;        // [n_inst][N] upstream gradient; null means -1 (Eq. 3)
+    const float* dS;        // [n_inst][N] upstream gradient; null: -dloss, or -1 (Eq. 3)
+    const float* dloss;     // [n_inst] upstream gradient of the loss, may be null (1)
+    float* loss_out;        // [n_inst] Eq. 3 in FP32, may be null
     Ctrl* ctrl;             // may be null (stateless evaluation)
     InstCtrl* ictrl;        // may be null (stateless evaluation)
     const InstInfo* info;   // [n_inst]
@@ -87,6 +92,7 @@ struct SminArgs {
     int32_t zero_H;
     int32_t update;         // schedule the AdamW update of this step
     int32_t every, restart;
+    int32_t mix;            // mix the candidates at learning-rate restarts
     double tau, lr0, decay, lr_min, beta1, beta2, weight_decay, conv_frac;
 };
 
@@ -110,6 +116,9 @@ struct VarArgs {
     float* v;
     float* U_out;             // [V][N], may be null
     float* g_out;             // [V][N] or [N][V], may be null
+    const float* dA_in;       // [V][N] dL/d(theta_norm) for the Eq. 5 backward op
+    uint64_t* vbits_out;      // [V][W] value rows of the binarize op, may be null
+    float* assign_out;        // [V][N] 0/1 values of the binarize op, may be null
     int32_t g_transposed;
     float beta1, beta2, one_minus_beta1, one_minus_beta2, eps;
     double inv_n;             // 1 / N (row means and the Eq. 5 backward multiply by it)
@@ -158,6 +167,6 @@ hipError_t launch_strided_rows(const uint64_t* src, int64_t rows, int w, int64_t
 hipError_t launch_rank(const int64_t* sat, int N, int32_t* order, hipStream_t st);
 hipError_t launch_select(const SelectArgs& a, int nblocks, hipStream_t st);
 
-enum { VOP_STEP = 0, VOP_GRAD = 1, VOP_ADJ = 2, VOP_BINARIZE = 3 };
+enum { VOP_STEP = 0, VOP_GRAD = 1, VOP_ADJ = 2, VOP_BINARIZE = 3, VOP_NORMBWD = 4 };
 
 } // namespace tsat

@@ -66,7 +66,7 @@ struct tsat_solver {
     DBuf H, H_last, table, S64, sat;
     DBuf ctrl, ictrl, ctrl_scr, witness;
     // scratch for stateless evaluations and the device-pointer API
-    DBuf lits_scr, H_scr, table_scr, S64_scr, sat_scr, tmp;
+    DBuf lits_scr, mu_scr, H_scr, table_scr, S64_scr, sat_scr, tmp;
     int32_t scr_Np = 0;
 
     // graph replay of two iterations (one per buffer parity)
@@ -121,6 +121,7 @@ static int32_t validate_params(const tsat_params* p)
     if (!(p->beta1 >= 0 && p->beta1 < 1 && p->beta2 >= 0 && p->beta2 < 1)) return fail(TSAT_E_ARG, "betas must be in [0, 1)");
     if (!(p->eps > 0) || !(p->lr0 >= 0) || !(p->lr_min >= 0)) return fail(TSAT_E_ARG, "eps must be > 0, learning rates >= 0");
     if (p->norm_mode != TSAT_MODE_MEAN && p->norm_mode != TSAT_MODE_NONE) return fail(TSAT_E_ARG, "norm_mode must be 0 or 1");
+    if (p->mix != 0 && p->mix != 1) return fail(TSAT_E_ARG, "mix must be 0 or 1");
     return TSAT_OK;
 }
 
@@ -263,6 +264,7 @@ static SminArgs smin_args(tsat_solver* s, const tsat_params& p, int32_t N, int32
     a.zero_H = 1;
     a.every = p.decay_every;
     a.restart = p.restart_every;
+    a.mix = p.mix;
     a.tau = p.tau;
     a.lr0 = p.lr0;
     a.decay = p.lr_decay;
@@ -347,6 +349,7 @@ static int32_t ensure_scratch(tsat_solver* s, int32_t N)
     const int32_t K1 = K1_of(s);
     const size_t ni = (size_t)s->st.n_inst;
     RET(s->lits_scr.reserve(((size_t)2 * s->st.V * W + 16) * 8, "scratch literal rows"));
+    RET(s->mu_scr.reserve((size_t)s->st.V * 8, "scratch row means"));
     if (Np > s->scr_Np) {
         RET(s->H_scr.alloc(ni * Np * K1 * 4, "scratch histogram"));
         HIPCHK(launch_fill_u32(s->H_scr.as<uint32_t>(), (int64_t)(ni * Np * K1), 0u, s->stream));
@@ -432,6 +435,8 @@ int32_t tsat_default_params(tsat_params* p)
     p->restart_every = 360;
     p->norm_mode = TSAT_MODE_MEAN;
     p->k_partial = 0;
+    p->mix = 0;
+    p->reserved = 0;
     return TSAT_OK;
 }
 
@@ -996,7 +1001,8 @@ int32_t tsat_device_clock_hz(tsat_solver* s, double* hz)
 
 // stateless forward + SmoothMin of literal rows `lits` (N candidates)
 static int32_t eval_rows(tsat_solver* s, const tsat_params& p, const uint64_t* lits, int32_t N, const float* dS,
-                         uint32_t* H_out, float* S32, double* S64, int64_t* sat, float* table, hipStream_t st)
+                         uint32_t* H_out, float* S32, double* S64, int64_t* sat, float* table, hipStream_t st,
+                         float* loss_out = nullptr, const float* dloss = nullptr)
 {
     const int32_t W = (N + 63) / 64, Np = 64 * W;
     uint32_t* planes = nullptr;
@@ -1014,6 +1020,8 @@ static int32_t eval_rows(tsat_solver* s, const tsat_params& p, const uint64_t* l
     a.S64_out = S64;
     a.sat_out = sat;
     a.dS = dS;
+    a.dloss = dloss;
+    a.loss_out = loss_out;
     a.update = 0;
     HIPCHK(launch_smin(a, st));
     return TSAT_OK;
@@ -1184,6 +1192,35 @@ int32_t tsat_get_state(tsat_solver* s, float* theta, float* m, float* v, int64_t
     return TSAT_OK;
 }
 
+int32_t tsat_get_adam_origin(tsat_solver* s, int64_t* origin)
+{
+    g_err.clear();
+    RET(need_batch(s));
+    if (!origin) return fail(TSAT_E_ARG, "origin is NULL");
+    RET(set_dev(s));
+    Ctrl c;
+    HIPCHK(hipMemcpyAsync(&c, s->ctrl.p, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    *origin = c.t_reset;
+    return TSAT_OK;
+}
+
+int32_t tsat_set_adam_origin(tsat_solver* s, int64_t origin)
+{
+    g_err.clear();
+    RET(need_batch(s));
+    RET(set_dev(s));
+    Ctrl c;
+    HIPCHK(hipMemcpyAsync(&c, s->ctrl.p, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (origin < 0 || origin > c.t) return fail(TSAT_E_ARG, "origin must be in [0, %lld]", (long long)c.t);
+    c.t_reset = origin;
+    HIPCHK(hipMemcpyAsync(s->ctrl.p, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->drop_graph();
+    return TSAT_OK;
+}
+
 int32_t tsat_eval(tsat_solver* s, const tsat_params* params, uint32_t* hist, double* S, double* loss)
 {
     g_err.clear();
@@ -1349,6 +1386,108 @@ int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
     va.lits_cur = s->lits_scr.as<uint64_t>();
     va.U_out = U;
     HIPCHK(launch_var(va, VOP_ADJ, var_blocks(s, s->st.V), st));
+    return TSAT_OK;
+}
+
+// Eq. 5 + Eq. 2 of caller logits into the scratch literal rows (and row
+// means), optionally also the value rows and 0/1 floats for the caller.
+static int32_t dev_binarize(tsat_solver* s, const float* theta, int32_t N, int32_t mode, uint64_t* vbits, float* assign,
+                            double* mu, hipStream_t st)
+{
+    RET(need_single(s));
+    RET(ensure_scratch(s, N));
+    RET(prepare_units(s, N));
+    const int32_t W = (N + 63) / 64;
+    tsat_params p = s->params;
+    p.norm_mode = mode;
+    VarArgs a = var_args(s, p, N, W, 64 * W);
+    a.theta = const_cast<float*>(theta); // read only by the binarize op
+    a.lits_next = s->lits_scr.as<uint64_t>();
+    a.mu_next = mu ? mu : s->mu_scr.as<double>();
+    a.vbits_out = vbits;
+    a.assign_out = assign;
+    HIPCHK(launch_var(a, VOP_BINARIZE, var_blocks(s, s->st.V), st));
+    return TSAT_OK;
+}
+
+static int32_t dev_args(tsat_solver* s, int32_t N, int32_t mode, const void* theta, float tau)
+{
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
+    if (N < 1 || N > TSAT_MAX_STEP_N) return fail(TSAT_E_ARG, "N must be in [1, %d]", TSAT_MAX_STEP_N);
+    if (mode != TSAT_MODE_MEAN && mode != TSAT_MODE_NONE) return fail(TSAT_E_ARG, "mode must be 0 or 1");
+    if (!theta) return fail(TSAT_E_ARG, "theta is NULL");
+    if (!(tau >= 0.f) || !std::isfinite(tau)) return fail(TSAT_E_ARG, "tau must be finite and >= 0");
+    return set_dev(s);
+}
+
+int32_t tsat_binarize_dev(tsat_solver* s, const float* theta, int32_t N, int32_t mode, uint64_t* bits, float* assign,
+                          double* mu, void* stream)
+{
+    g_err.clear();
+    RET(dev_args(s, N, mode, theta, 0.f));
+    if (!bits && !assign && !mu) return fail(TSAT_E_ARG, "no output");
+    RET(check_row_offsets(s, (N + 63) / 64));
+    return dev_binarize(s, theta, N, mode, bits, assign, mu, (hipStream_t)stream);
+}
+
+int32_t tsat_norm_backward_dev(tsat_solver* s, const float* theta, const float* dA, int32_t N, int32_t mode, float* g,
+                               void* stream)
+{
+    g_err.clear();
+    RET(dev_args(s, N, mode, theta, 0.f));
+    if (!dA || !g) return fail(TSAT_E_ARG, "NULL dA or g");
+    const int32_t W = (N + 63) / 64;
+    tsat_params p = s->params;
+    p.norm_mode = mode;
+    VarArgs a = var_args(s, p, N, W, 64 * W);
+    a.theta = const_cast<float*>(theta); // read only by this op
+    a.dA_in = dA;
+    a.g_out = g;
+    HIPCHK(launch_var(a, VOP_NORMBWD, var_blocks(s, s->st.V), (hipStream_t)stream));
+    return TSAT_OK;
+}
+
+int32_t tsat_loss_dev(tsat_solver* s, const float* theta, int32_t N, float tau, int32_t mode, float* loss, float* S,
+                      uint64_t* bits, void* stream)
+{
+    g_err.clear();
+    RET(dev_args(s, N, mode, theta, tau));
+    if (!loss) return fail(TSAT_E_ARG, "loss is NULL");
+    RET(check_row_offsets(s, (N + 63) / 64));
+    hipStream_t st = (hipStream_t)stream;
+    RET(dev_binarize(s, theta, N, mode, bits, nullptr, nullptr, st));
+    tsat_params p = s->params;
+    p.tau = tau;
+    p.norm_mode = mode;
+    return eval_rows(s, p, s->lits_scr.as<uint64_t>(), N, nullptr, nullptr, S, nullptr, nullptr, nullptr, st, loss);
+}
+
+int32_t tsat_loss_backward_dev(tsat_solver* s, const float* theta, int32_t N, float tau, int32_t mode,
+                               const float* dloss, float* g, float* U, void* stream)
+{
+    g_err.clear();
+    RET(dev_args(s, N, mode, theta, tau));
+    if (!g) return fail(TSAT_E_ARG, "g is NULL");
+    const int32_t W = (N + 63) / 64, Np = 64 * W;
+    if ((size_t)K1_of(s) * Np * 4 > 64 * 1024) return fail(TSAT_E_ARG, "table exceeds 64 KiB");
+    RET(check_row_offsets(s, W));
+    hipStream_t st = (hipStream_t)stream;
+    RET(dev_binarize(s, theta, N, mode, nullptr, nullptr, nullptr, st));
+    tsat_params p = s->params;
+    p.tau = tau;
+    p.norm_mode = mode;
+    RET(eval_rows(s, p, s->lits_scr.as<uint64_t>(), N, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  s->table_scr.as<float>(), st, nullptr, dloss));
+    VarArgs va = var_args(s, p, N, W, Np);
+    va.tbl = s->table_scr.as<float>();
+    va.theta = const_cast<float*>(theta); // read only by the gradient op
+    va.lits_cur = s->lits_scr.as<uint64_t>();
+    va.mu_cur = s->mu_scr.as<double>();
+    va.U_out = U;
+    va.g_out = g;
+    va.g_transposed = 0;
+    HIPCHK(launch_var(va, VOP_GRAD, var_blocks(s, s->st.V), st));
     return TSAT_OK;
 }
 

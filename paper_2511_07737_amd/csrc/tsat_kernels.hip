@@ -292,7 +292,12 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
         const int64_t e = a.every > 0 ? phase / a.every : 0;
         double lr = a.lr0 * pow(a.decay, (double)e);
         if (lr < a.lr_min) lr = a.lr_min;
-        const double tt = (double)(t + 1);
+        // assignment mixing at a restart replaces the update and starts a
+        // fresh AdamW: the bias corrections count from the next iteration
+        const bool mixing = a.mix && a.restart > 0 && t > 0 && phase == 0;
+        ctrl->mixing = mixing ? 1 : 0;
+        if (mixing) ctrl->t_reset = t + 1;
+        const double tt = (double)(t - ctrl->t_reset + 1);
         const double bc1 = 1.0 - pow(a.beta1, tt);
         const double bc2 = 1.0 - pow(a.beta2, tt);
         ctrl->lr = lr;
@@ -341,7 +346,9 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
         loss += S;
         if (sat > best) { best = sat; bidx = i; }
         if (unsat == 0 && i < satc) satc = i;
-        const double up = a.dS ? (double)a.dS[ob + i] : -1.0;
+        // dL/dS_i: given per candidate, or -dloss (Eq. 3 scaled by the
+        // upstream gradient of the loss), or -1 (Eq. 3)
+        const double up = a.dS ? (double)a.dS[ob + i] : (a.dloss ? -(double)a.dloss[b] : -1.0);
         for (int r = 0; r < K1; ++r) {
             if (tb) {
                 double tv = 0.0;
@@ -371,6 +378,7 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
         }
         __syncthreads();
     }
+    if (tid == 0 && a.loss_out) a.loss_out[b] = (float)(-s_loss[0]);
     if (tid == 0 && ic) {
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
         if (ic->start_time == 0) ic->start_time = now;
@@ -413,7 +421,7 @@ __global__ __launch_bounds__(256) void smin_kernel(SminArgs a)
 // by the lane that owns it, and the row's reductions stay in the wave.
 // ---------------------------------------------------------------------------
 
-enum { OP_STEP = 0, OP_GRAD = 1, OP_ADJ = 2, OP_BINARIZE = 3 };
+enum { OP_STEP = 0, OP_GRAD = 1, OP_ADJ = 2, OP_BINARIZE = 3, OP_NORMBWD = 4 };
 
 struct StepScalars {
     float f_decay, f_step, f_isbc2;
@@ -484,6 +492,28 @@ __device__ __forceinline__ void load_row(const VarArgs& a, uint32_t v, uint32_t 
     }
 }
 
+// Eq. 5 backward of one variable row: g = U / mu - (sum_i U_i theta_i) /
+// (N mu^2) in mean mode (inside the clamp the mean is a constant and the
+// second term is dropped), g = U without normalization.
+template <int J>
+__device__ __forceinline__ void norm_backward_row(const VarArgs& a, const float (&th)[J], const double (&U)[J],
+                                                  double mu, bool clamped, float (&g)[J])
+{
+    if (a.mode == 1) {
+        double ut = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) ut += U[j] * (double)th[j];
+        ut = wave_sum(ut);
+        const double inv_mu = 1.0 / mu;
+        const double corr = clamped ? 0.0 : ut * inv_mu * inv_mu * a.inv_n;
+#pragma unroll
+        for (int j = 0; j < J; ++j) g[j] = (float)(U[j] * inv_mu - corr);
+    } else {
+#pragma unroll
+        for (int j = 0; j < J; ++j) g[j] = (float)U[j];
+    }
+}
+
 // Everything after U: stores of U (adjoint op), Eq. 5 backward, stores of g
 // (gradient op), AdamW, witness, new row mean, re-binarization (step op).
 template <int J, int OP>
@@ -501,21 +531,8 @@ __device__ __forceinline__ void var_tail(const VarArgs& a, const StepScalars& c,
         }
         if (OP == OP_ADJ) return;
     }
-    // Eq. 5 backward: g = U / mu - (sum_i U_i theta_i) / (N mu^2)
     float g[J];
-    if (a.mode == 1) {
-        double ut = 0.0;
-#pragma unroll
-        for (int j = 0; j < J; ++j) ut += U[j] * (double)th[j];
-        ut = wave_sum(ut);
-        const double inv_mu = 1.0 / mu;
-        const double corr = clamped ? 0.0 : ut * inv_mu * inv_mu * a.inv_n;
-#pragma unroll
-        for (int j = 0; j < J; ++j) g[j] = (float)(U[j] * inv_mu - corr);
-    } else {
-#pragma unroll
-        for (int j = 0; j < J; ++j) g[j] = (float)U[j];
-    }
+    norm_backward_row<J>(a, th, U, mu, clamped, g);
     if (OP == OP_GRAD) {
         if (a.g_out) {
 #pragma unroll
@@ -632,6 +649,62 @@ __device__ __forceinline__ void advance_step(const VarArgs& a)
     }
 }
 
+// Assignment mixing at a learning-rate restart (the mixing paragraph of
+// Sec. IV-A and its equation): in every variable row, each candidate other
+// than its instance's best one i* (most satisfied clauses at this
+// iteration's forward pass, lower index on ties) becomes the average of
+// itself and i*; the AdamW moments restart from zero; the new row means and
+// bits follow.  Replaces the gradient step of the iteration; one wave per
+// variable, every variable (heavy ones included).
+template <int J>
+__device__ void mix_rows(const VarArgs& a)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const int N = a.N, W = a.W;
+    for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        const VarInst vi = var_instance<OP_STEP>(a, v);
+        if (vi.frozen) {
+            keep_variable<J>(a, v, lane);
+            continue;
+        }
+        const int32_t best = a.ictrl ? (int32_t)uniform((uint32_t)sload(&a.ictrl[vi.inst].best_cand)) : 0;
+        const float* row = a.theta + (size_t)v * N;
+        const double star = (double)row[best]; // same address in every lane
+        float th[J];
+        bool valid[J];
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = 64 * j + (int)lane;
+            valid[j] = i < N;
+            float x = valid[j] ? __builtin_nontemporal_load(row + i) : 0.f;
+            if (valid[j] && i != best) x = (float)(0.5 * ((double)x + star));
+            th[j] = x;
+            if (valid[j]) {
+                const size_t idx = (size_t)v * N + i;
+                __builtin_nontemporal_store(x, a.theta + idx);
+                __builtin_nontemporal_store(0.f, a.m + idx);
+                __builtin_nontemporal_store(0.f, a.v + idx);
+            }
+            s += (double)x;
+        }
+        if (vi.witness && lane == 0) {
+            const uint64_t w = a.lits_cur[(size_t)(2 * v) * W + (vi.wcand >> 6)];
+            a.witness[v] = (uint8_t)((w >> (vi.wcand & 63)) & 1u);
+        }
+        bool pos = true;
+        if (a.mode == 1) {
+            const double mu2 = wave_sum(s) * a.inv_n;
+            if (lane == 0) a.mu_next[v] = mu2;
+            pos = mu2 >= 0.0;
+        }
+        write_bits<J>(a, v, lane, th, valid, pos);
+    }
+    advance_step(a);
+}
+
 // theta -> row means and literal rows (initialization, set_logits/state).
 template <int J>
 __global__ __launch_bounds__(256) void binarize_kernel(VarArgs a)
@@ -652,13 +725,56 @@ __global__ __launch_bounds__(256) void binarize_kernel(VarArgs a)
         }
         bool pos = true;
         if (a.mode == 1) {
-            const double mu = wave_sum(s) / (double)a.N;
+            // the same arithmetic as the update's new row mean, so that a
+            // state set from a checkpoint binarizes exactly as the run did
+            const double mu = wave_sum(s) * a.inv_n;
             if (lane == 0) a.mu_next[v] = mu;
             pos = mu >= 0.0;
         } else if (lane == 0) {
             a.mu_next[v] = 1.0;
         }
         write_bits<J>(a, v, lane, th, valid, pos);
+        if (a.vbits_out || a.assign_out) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const bool b = valid[j] && (pos ? th[j] > 0.f : th[j] < 0.f);
+                const uint64_t bal = ballot64(b);
+                if (a.vbits_out && j < a.W && lane == 0) a.vbits_out[(size_t)v * a.W + j] = bal;
+                if (a.assign_out && valid[j]) a.assign_out[(size_t)v * a.N + 64 * j + lane] = b ? 1.f : 0.f;
+            }
+        }
+    }
+}
+
+// Eq. 5 backward of caller arrays (device-pointer API): g from theta and
+// dA = dL/d(theta_norm), the gradient the straight-through estimator passes
+// through Eq. 2.  The row mean is formed exactly as binarize_kernel forms it.
+template <int J>
+__global__ __launch_bounds__(256) void norm_backward_kernel(VarArgs a)
+{
+    const uint32_t lane = __lane_id();
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    for (uint32_t v = wave0; v < (uint32_t)a.V; v += nwaves) {
+        float th[J];
+        double U[J];
+        bool valid[J];
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = 64 * j + (int)lane;
+            valid[j] = i < a.N;
+            th[j] = valid[j] ? a.theta[(size_t)v * a.N + i] : 0.f;
+            U[j] = valid[j] ? (double)a.dA_in[(size_t)v * a.N + i] : 0.0;
+            s += (double)th[j];
+        }
+        bool clamped = false;
+        const double mu = a.mode == 1 ? clamp_mu(wave_sum(s) * a.inv_n, clamped) : 1.0;
+        float g[J];
+        norm_backward_row<J>(a, th, U, mu, clamped, g);
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (valid[j]) a.g_out[(size_t)v * a.N + 64 * j + lane] = g[j];
     }
 }
 
@@ -670,6 +786,10 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
     extern __shared__ float s_tbl[]; // [K1][Np] (one instance)
     if (OP == OP_STEP && a.ctrl->stop) {
         copy_bits_on_stop(a);
+        return;
+    }
+    if (OP == OP_STEP && a.ctrl->mixing) {
+        mix_rows<J>(a);
         return;
     }
     if (!MULTI) {
@@ -752,7 +872,7 @@ __global__ __launch_bounds__(256) void var_kernel(VarArgs a)
 template <int J, int OP>
 __global__ __launch_bounds__(256) void var_heavy_part_kernel(VarArgs a)
 {
-    if (OP == OP_STEP && a.ctrl->stop) return;
+    if (OP == OP_STEP && (a.ctrl->stop || a.ctrl->mixing)) return; // the main kernel covers both
     const uint32_t lane = __lane_id();
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
     const uint32_t nwaves = uniform(gridDim.x * 4u);
@@ -806,7 +926,7 @@ __global__ __launch_bounds__(256) void var_heavy_part_kernel(VarArgs a)
 template <int J, int OP>
 __global__ __launch_bounds__(256) void var_heavy_tail_kernel(VarArgs a)
 {
-    if (OP == OP_STEP && a.ctrl->stop) return;
+    if (OP == OP_STEP && (a.ctrl->stop || a.ctrl->mixing)) return; // the main kernel covers both
     const uint32_t lane = __lane_id();
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
     const uint32_t nwaves = uniform(gridDim.x * 4u);
@@ -963,6 +1083,10 @@ __device__ __forceinline__ void var_pure_body(const VarArgs& a)
 {
     if (OP == OP_STEP && a.ctrl->stop) {
         copy_bits_on_stop(a);
+        return;
+    }
+    if (OP == OP_STEP && a.ctrl->mixing) {
+        mix_rows<J>(a);
         return;
     }
     const uint32_t lane = __lane_id();
@@ -1268,6 +1392,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
         copy_bits_on_stop(a);
         return;
     }
+    if (OP == OP_STEP && a.ctrl->mixing) {
+        mix_rows<J>(a);
+        return;
+    }
     constexpr int G = 2;       // records per scalar-load group
     constexpr int K1 = KW + 1; // R in 0..KW
     const uint32_t lane = __lane_id();
@@ -1461,6 +1589,10 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
         copy_bits_on_stop(a);
         return;
     }
+    if (OP == OP_STEP && a.ctrl->mixing) {
+        mix_rows<J>(a);
+        return;
+    }
     constexpr int K1 = KW + 1;     // R in 0..KW
     constexpr uint32_t kChunk = 4; // variables per wave work item (measured best of 2, 4, 8, 16)
     const uint32_t lane = __lane_id();
@@ -1631,6 +1763,10 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
 {
     if (OP == OP_STEP && a.ctrl->stop) {
         copy_bits_on_stop(a);
+        return;
+    }
+    if (OP == OP_STEP && a.ctrl->mixing) {
+        mix_rows<1>(a);
         return;
     }
     constexpr int K1 = KW + 1;
@@ -2059,6 +2195,7 @@ static hipError_t launch_var_jm(const VarArgs& a, int op, int blocks, hipStream_
     case OP_STEP: hipLaunchKernelGGL((var_kernel<J, OP_STEP, MULTI>), dim3(blocks), dim3(256), lds, st, a); break;
     case OP_GRAD: hipLaunchKernelGGL((var_kernel<J, OP_GRAD, MULTI>), dim3(blocks), dim3(256), lds, st, a); break;
     case OP_ADJ: hipLaunchKernelGGL((var_kernel<J, OP_ADJ, MULTI>), dim3(blocks), dim3(256), lds, st, a); break;
+    case OP_NORMBWD: hipLaunchKernelGGL((norm_backward_kernel<J>), dim3(blocks), dim3(256), 0, st, a); break;
     default: hipLaunchKernelGGL((binarize_kernel<J>), dim3(blocks), dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
@@ -2085,7 +2222,7 @@ static hipError_t launch_heavy(const VarArgs& a, int op, bool tail, int blocks, 
 template <int J>
 static hipError_t launch_var_j(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
-    const bool split = a.heavy && a.n_chunks > 0 && op != OP_BINARIZE;
+    const bool split = a.heavy && a.n_chunks > 0 && op != OP_BINARIZE && op != OP_NORMBWD;
     if (split) {
         // partial sums of the heavy variables, then the light variables, then the heavy tails
         hipError_t e = launch_heavy<J>(a, op, false, std::max(1, std::min((a.n_chunks + 3) / 4, blocks)), st);
@@ -2206,14 +2343,15 @@ static hipError_t launch_plane_j(const VarArgs& a, int op, int blocks, hipStream
 
 hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
-    if (a.occ_cid && a.planes && op != OP_BINARIZE && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
+    const bool rowwise = op == OP_BINARIZE || op == OP_NORMBWD; // no gather
+    if (a.occ_cid && a.planes && !rowwise && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
         switch (a.W) {
         case 1: return launch_plane_j<1>(a, op, blocks, st);
         case 2: return launch_plane_j<2>(a, op, blocks, st);
         default: return launch_plane_j<4>(a, op, blocks, st);
         }
     }
-    const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;
+    const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && !rowwise;
     switch (a.W) {
     case 1: return pure ? launch_pure_j<1>(a, op, blocks, st) : launch_var_j<1>(a, op, blocks, st);
     case 2: return pure ? launch_pure_j<2>(a, op, blocks, st) : launch_var_j<2>(a, op, blocks, st);
@@ -2249,7 +2387,8 @@ static int occupancy_j(const VarArgs& a, bool pure)
 
 int var_occupancy(const VarArgs& a, int op)
 {
-    if (a.occ_cid && a.planes && op != OP_BINARIZE && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
+    const bool rowwise = op == OP_BINARIZE || op == OP_NORMBWD; // no gather
+    if (a.occ_cid && a.planes && !rowwise && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
         const bool k2 = a.pure_k == 2, win = a.window != 0;
         if (pair_rows(a))
             return k2 ? occupancy_of(var_window_pair_kernel<2, OP_STEP>, 0) : occupancy_of(var_window_pair_kernel<3, OP_STEP>, 0);
@@ -2259,7 +2398,7 @@ int var_occupancy(const VarArgs& a, int op)
         default: return occupancy_of(k2 ? plane_kernel_ptr<4, 2, OP_STEP, false>(win) : plane_kernel_ptr<4, 3, OP_STEP, false>(win), 0);
         }
     }
-    const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && op != OP_BINARIZE;
+    const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && !rowwise;
     switch (a.W) {
     case 1: return occupancy_j<1>(a, pure);
     case 2: return occupancy_j<2>(a, pure);

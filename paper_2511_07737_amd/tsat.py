@@ -47,6 +47,7 @@ class Params(ct.Structure):
         ("beta1", _f64), ("beta2", _f64), ("eps", _f64), ("weight_decay", _f64),
         ("converge_frac", _f64),
         ("decay_every", _i32), ("restart_every", _i32), ("norm_mode", _i32), ("k_partial", _i32),
+        ("mix", _i32), ("reserved", _i32),
     ]
 
 
@@ -129,6 +130,12 @@ _SIGS = [
     ("tsat_pack_dev", _i32, [_P, _P, _i32, _P, _P]),
     ("tsat_fwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_bwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
+    ("tsat_binarize_dev", _i32, [_P, _P, _i32, _i32, _P, _P, _P, _P]),
+    ("tsat_get_adam_origin", _i32, [_P, _P]),
+    ("tsat_set_adam_origin", _i32, [_P, _i64]),
+    ("tsat_norm_backward_dev", _i32, [_P, _P, _P, _i32, _i32, _P, _P]),
+    ("tsat_loss_dev", _i32, [_P, _P, _i32, _f32, _i32, _P, _P, _P, _P]),
+    ("tsat_loss_backward_dev", _i32, [_P, _P, _i32, _f32, _i32, _P, _P, _P, _P]),
     ("tsat_set_timing", _i32, [_P, _i32]),
     ("tsat_get_timing", _i32, [_P, ct.POINTER(_f64), ct.POINTER(_i32)]),
     ("tsat_copy_calibrate", _i32, [_P, _i64, ct.POINTER(_f64)]),
@@ -448,6 +455,14 @@ class Solver:
         _check(lib().tsat_get_state(self._h, _ptr(th), _ptr(m), _ptr(v), ct.byref(t)))
         return th, m, v, int(t.value)
 
+    def get_adam_origin(self) -> int:
+        t0 = _i64()
+        _check(lib().tsat_get_adam_origin(self._h, ct.byref(t0)))
+        return int(t0.value)
+
+    def set_adam_origin(self, origin: int) -> None:
+        _check(lib().tsat_set_adam_origin(self._h, int(origin)))
+
     def get_bits(self) -> np.ndarray:
         out = np.empty((self.V, (self.N + 63) // 64), dtype=np.uint64)
         _check(lib().tsat_get_bits(self._h, _ptr(out)))
@@ -481,6 +496,24 @@ class Solver:
 
     def bwd_dev(self, bits_ptr: int, n: int, tau: float, dS_ptr: int, U_ptr: int, stream: int | None = None) -> None:
         _check(lib().tsat_bwd_dev(self._h, bits_ptr, int(n), float(tau), dS_ptr, U_ptr, stream))
+
+    def binarize_dev(self, theta_ptr: int, n: int, mode: int, bits_ptr: int | None, assign_ptr: int | None,
+                     mu_ptr: int | None, stream: int | None = None) -> None:
+        _check(lib().tsat_binarize_dev(self._h, theta_ptr, int(n), int(mode), bits_ptr, assign_ptr, mu_ptr, stream))
+
+    def norm_backward_dev(self, theta_ptr: int, dA_ptr: int, n: int, mode: int, g_ptr: int,
+                          stream: int | None = None) -> None:
+        _check(lib().tsat_norm_backward_dev(self._h, theta_ptr, dA_ptr, int(n), int(mode), g_ptr, stream))
+
+    def loss_dev(self, theta_ptr: int, n: int, tau: float, mode: int, loss_ptr: int, S_ptr: int | None,
+                 bits_ptr: int | None, stream: int | None = None) -> None:
+        _check(lib().tsat_loss_dev(self._h, theta_ptr, int(n), float(tau), int(mode), loss_ptr, S_ptr, bits_ptr,
+                                   stream))
+
+    def loss_backward_dev(self, theta_ptr: int, n: int, tau: float, mode: int, dloss_ptr: int | None, g_ptr: int,
+                          U_ptr: int | None, stream: int | None = None) -> None:
+        _check(lib().tsat_loss_backward_dev(self._h, theta_ptr, int(n), float(tau), int(mode), dloss_ptr, g_ptr,
+                                            U_ptr, stream))
 
     # timing ---------------------------------------------------------------
     def set_timing(self, enable: bool) -> None:

@@ -86,22 +86,25 @@ def sub_cnf(cnf: gen.CNF, vars0: np.ndarray) -> gen.CNF:
     return gen.CNF.from_clauses(cnf.num_vars, clauses)
 
 
-def adam_reference(theta, m, v, g, t, p):
-    """Oracle AdamW on float64 copies; t is the 0-based iteration index."""
+def adam_reference(theta, m, v, g, t, p, count=None):
+    """Oracle AdamW on float64 copies; t is the 0-based iteration index, count
+    the bias-correction count (t + 1 from a fresh optimizer)."""
     th = theta.astype(np.float64).copy()
     mm = m.astype(np.float64).copy()
     vv = v.astype(np.float64).copy()
     lr = orc.lr(t, orc.default_params(lr0=p.lr0, decay=p.lr_decay, every=p.decay_every,
                                       restart=p.restart_every, lr_min=p.lr_min))
-    orc.adamw(th, mm, vv, g.astype(np.float64), lr, t + 1, p.beta1, p.beta2, p.eps, p.weight_decay)
+    orc.adamw(th, mm, vv, g.astype(np.float64), lr, t + 1 if count is None else count, p.beta1, p.beta2, p.eps,
+              p.weight_decay)
     return th, mm, vv, lr
 
 
-def adam_bounds(theta, m, v, g, t, p, lr, v_new):
+def adam_bounds(theta, m, v, g, t, p, lr, v_new, count=None):
     th = np.abs(theta.astype(np.float64))
     g64 = g.astype(np.float64)
-    bc1 = 1 - p.beta1 ** (t + 1)
-    bc2 = 1 - p.beta2 ** (t + 1)
+    n = t + 1 if count is None else count
+    bc1 = 1 - p.beta1 ** n
+    bc2 = 1 - p.beta2 ** n
     m_abs = p.beta1 * np.abs(m) + (1 - p.beta1) * np.abs(g64)
     v_abs = p.beta2 * np.abs(v) + (1 - p.beta2) * g64 * g64
     step = (lr / bc1) * m_abs / (np.sqrt(np.abs(v_new)) / np.sqrt(bc2) + p.eps)

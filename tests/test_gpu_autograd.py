@@ -121,20 +121,116 @@ def test_structured_config_fd_and_oracle(env):
     assert (np.abs(got - fd) <= fd_err + 1e-5 * scale).all()
 
 
-def test_full_chain_gradient(env):
-    """theta -> Eq. 5 -> STE binarize -> layer -> Eq. 3: theta.grad vs the oracle g."""
+def _chain_reference(oc, th, mode, tau=1.0):
+    """Oracle loss and dL/dtheta of theta -> Eq. 5 -> Eq. 2 -> Eq. 1 -> Eq. 4 -> Eq. 3,
+    and the error scale a_g of the gradient."""
+    p = orc.default_params(mode=mode, tau=tau)
+    ref = orc.step(oc, th.astype(np.float64), np.zeros_like(th, np.float64), np.zeros_like(th, np.float64), 0, p)
+    b, mu = orc.binarize(th.astype(np.float64), mode)
+    _, table, _ = orc.smoothmin(orc.histogram(oc, b), tau)
+    aU = abs_adjoint(oc, b, table)
+    ag = grad_bound(aU, th, mu if mode == orc.MODE_MEAN else np.ones_like(mu), ref["g"])
+    return ref, b, mu, ag
+
+
+@pytest.mark.parametrize("normalize", [True, False])
+def test_full_chain_gradient(env, normalize):
+    """theta -> Eq. 5 -> STE binarize -> layer -> Eq. 3 in one Function (loss and
+    its fused backward in the library): loss and theta.grad vs the oracle."""
     torch, solver, ag = env
     cnf = gen.planted_ksat(200, 800, 3, seed=1)
     solver.load(cnf)
     oc = orc.Cnf.from_gen(cnf)
     th, _, _ = make_state(200, 64, 1001, t_moments=False, min_abs_mu=1e-2)
+    mode = orc.MODE_MEAN if normalize else orc.MODE_NONE
     T = torch.tensor(th, device="cuda", requires_grad=True)
-    loss = ag.loss_of(T, solver, 1.0)
-    loss.backward()
-    ref = orc.step(oc, th.astype(np.float64), np.zeros((200, 64)), np.zeros((200, 64)), 0)
+    loss = ag.loss_of(T, solver, 1.0, normalize=normalize)
+    (2.5 * loss).backward()  # an upstream gradient other than 1
+    ref, _, _, a_g = _chain_reference(oc, th, mode)
     assert abs(loss.item() - ref["loss"]) <= 1e-5 * abs(ref["loss"])
-    b, mu = orc.binarize(th.astype(np.float64))
-    _, table, _ = orc.smoothmin(orc.histogram(oc, b), 1.0)
-    ag_b = grad_bound(abs_adjoint(oc, b, table), th, mu, ref["g"])
     g = T.grad.cpu().numpy()
-    assert (np.abs(g - ref["g"]) <= TOL_GRAD * ag_b + 1e-30).all(), np.abs(g - ref["g"]).max()
+    assert (np.abs(g - 2.5 * ref["g"]) <= TOL_GRAD * 2.5 * a_g + 1e-30).all(), np.abs(g - 2.5 * ref["g"]).max()
+
+
+@pytest.mark.parametrize("normalize", [True, False])
+def test_composed_chain_gradient(env, normalize):
+    """The same chain composed from its pieces: binarize (Eq. 5, Eq. 2 with the
+    STE and the Eq. 5 backward) feeding the SmoothMin layer; the loss sum is
+    formed by the test."""
+    torch, solver, ag = env
+    cnf = mixed_cnf()
+    solver.load(cnf)
+    oc = orc.Cnf.from_gen(cnf)
+    th, _, _ = make_state(cnf.num_vars, 100, 1003, t_moments=False, min_abs_mu=1e-2)
+    mode = tsat.MODE_MEAN if normalize else tsat.MODE_NONE
+    T = torch.tensor(th, device="cuda", requires_grad=True)
+    A = ag.binarize(T, solver, mode)
+    S = ag.smoothmin_sat(A, solver, 1.0)
+    loss = -S.sum()
+    loss.backward()
+    ref, b, _, a_g = _chain_reference(oc, th, mode)
+    assert np.array_equal(A.detach().cpu().numpy(), b.astype(np.float32))
+    assert abs(loss.item() - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+    g = T.grad.cpu().numpy()
+    assert (np.abs(g - ref["g"]) <= TOL_GRAD * a_g + 1e-30).all(), np.abs(g - ref["g"]).max()
+
+
+@pytest.mark.parametrize("N", [1, 64, 100, 256])
+def test_binarize_and_norm_backward_dev(env, N):
+    """The device-pointer Eq. 5 / Eq. 2 and Eq. 5 backward calls against the oracle:
+    bits and 0/1 values exact, row means to FP64 rounding, g within 1e-5 of its
+    term sizes; a zero-mean row takes the clamp."""
+    torch, solver, _ = env
+    cnf = gen.planted_ksat(300, 1200, 3, seed=5)
+    solver.load(cnf)
+    th, _, _ = make_state(300, N, 1100 + N, t_moments=False)
+    if N > 1:
+        th[7] = 0.0  # mean 0: clamped to +1e-12, every entry maps to 0
+        th[8, :] = np.float32(0.5)
+        th[8, 0] = np.float32(-0.5 * (N - 1))  # exact zero mean with nonzero entries
+    rng = np.random.default_rng(N)
+    dA = rng.standard_normal(size=(300, N)).astype(np.float32)
+    W = (N + 63) // 64
+    stream = torch.cuda.current_stream().cuda_stream
+    T = torch.tensor(th, device="cuda")
+    for mode in (tsat.MODE_MEAN, tsat.MODE_NONE):
+        bits = torch.empty((300, W), dtype=torch.int64, device="cuda")
+        A = torch.empty((300, N), dtype=torch.float32, device="cuda")
+        mu = torch.empty(300, dtype=torch.float64, device="cuda")
+        solver.binarize_dev(T.data_ptr(), N, mode, bits.data_ptr(), A.data_ptr(), mu.data_ptr(), stream)
+        b_ref, mu_ref = orc.binarize(th.astype(np.float64), mode)
+        got_bits = tsat.unpack_bits(bits.cpu().numpy().view(np.uint64), N)
+        assert np.array_equal(got_bits, b_ref)
+        assert np.array_equal(A.cpu().numpy(), b_ref.astype(np.float32))
+        if mode == tsat.MODE_MEAN:
+            assert np.allclose(mu.cpu().numpy(), th.astype(np.float64).mean(axis=1), rtol=1e-12, atol=1e-15)
+        g = torch.empty_like(T)
+        D = torch.tensor(dA, device="cuda")
+        solver.norm_backward_dev(T.data_ptr(), D.data_ptr(), N, mode, g.data_ptr(), stream)
+        g_ref = orc.norm_backward(th.astype(np.float64), dA.astype(np.float64), mode)
+        if mode == tsat.MODE_MEAN:
+            m = th.astype(np.float64).mean(axis=1, keepdims=True)
+            clamped = np.abs(m) < 1e-12
+            m = np.where(clamped, np.where(m >= 0, 1e-12, -1e-12), m)
+            corr = np.where(clamped, 0.0, (np.abs(dA) * np.abs(th)).sum(axis=1, keepdims=True) / (N * m * m))
+            scale = np.abs(dA) / np.abs(m) + corr + np.abs(g_ref)
+        else:
+            scale = np.abs(g_ref)
+        assert (np.abs(g.cpu().numpy() - g_ref) <= 1e-5 * scale + 1e-30).all()
+
+
+def test_device_calls_reject_bad_arguments(env):
+    torch, solver, _ = env
+    cnf = gen.planted_ksat(50, 200, 3, seed=2)
+    solver.load(cnf)
+    T = torch.zeros((50, 8), dtype=torch.float32, device="cuda")
+    out = torch.empty((), dtype=torch.float32, device="cuda")
+    with pytest.raises(tsat.TsatError) as e:
+        solver.loss_dev(T.data_ptr(), 8, -1.0, tsat.MODE_MEAN, out.data_ptr(), None, None)
+    assert e.value.code == tsat.E_ARG
+    with pytest.raises(tsat.TsatError) as e:
+        solver.binarize_dev(T.data_ptr(), 8, 5, None, None, None)
+    assert e.value.code == tsat.E_ARG
+    with pytest.raises(tsat.TsatError) as e:
+        solver.loss_backward_dev(T.data_ptr(), 0, 1.0, tsat.MODE_MEAN, None, T.data_ptr(), None)
+    assert e.value.code == tsat.E_ARG
