@@ -49,6 +49,7 @@ extern "C" {
 
 #define TSAT_MAX_WIDTH 32 /* widest clause (after de-duplication) */
 #define TSAT_MAX_STEP_N 1024 /* candidates per batch for the gradient step */
+#define TSAT_NOALLOC_SCRATCH_BYTES (4u << 20) /* fixed device scratch of tsat_fwd_dev_noalloc, per GPU */
 
 typedef struct tsat_solver tsat_solver;
 
@@ -393,6 +394,22 @@ int32_t tsat_loss_dev(tsat_solver* s, const float* theta, int32_t N, float tau, 
  * receives dloss * dLoss/d(theta/mu). */
 int32_t tsat_loss_backward_dev(tsat_solver* s, const float* theta, int32_t N, float tau, int32_t mode,
                                const float* dloss, float* g, float* U, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward of tsat_fwd_dev with the same arguments, outputs and results
+ * (bitwise), but it allocates nothing.  The literal rows are read straight
+ * from `bits` (a negated literal is the complement of its variable's row),
+ * and the histogram accumulator and the forward work units live in one
+ * fixed device array of TSAT_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends and shared by every call on that GPU: calls that overlap in
+ * time on one GPU (any solver, any stream) race and must be ordered by the
+ * caller.  Each call clears what it needs.  1 <= N <= TSAT_MAX_STEP_N;
+ * E_ARG when the accumulator ((64 ceil(N/64)) x (max width + 1) x 4 bytes)
+ * plus the work units (24 bytes per unit, about C / 8000 units per width
+ * bucket at N = 256) exceed the array; E_STATE as tsat_fwd_dev. */
+int32_t tsat_fwd_dev_noalloc(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, float* S, uint32_t* hist,
+                             void* stream);
 
 /* --------------------------------------------------- learned proposal --- */
 /*

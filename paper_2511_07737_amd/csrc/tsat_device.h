@@ -73,6 +73,7 @@ struct FwdArgs {
     const InstCtrl* ictrl;  // may be null
     uint32_t* planes;       // null, or [Cb][2][plane_stride]: bits 0 and 1 of R per clause (widths 2, 3)
     int32_t plane_stride;   // dwords per plane row (2 J, J the update kernel's words per candidate row)
+    int32_t vrows;          // bits32 holds value rows only ([V][W2]); not-x is the complement
 };
 
 struct SminArgs {
@@ -155,6 +156,10 @@ struct SelectArgs {
 
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st);
 hipError_t launch_smin(const SminArgs& a, hipStream_t st);
+hipError_t launch_fwd_units(FwdUnit* u, int64_t n, int64_t per, int64_t Cb, hipStream_t st);
+// device address of the allocation-free entry point's fixed scratch array on
+// `device` (which must be current); looked up once per device
+hipError_t noalloc_scratch_address(int device, void** out);
 hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st);
 int var_occupancy(const VarArgs& a, int op); // resident 256-thread blocks per CU of the step kernel
 hipError_t launch_expand(const uint64_t* bits, int64_t V, int W, int N, uint64_t* lits, hipStream_t st);

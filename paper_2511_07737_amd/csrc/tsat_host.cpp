@@ -68,6 +68,8 @@ struct tsat_solver {
     // scratch for stateless evaluations and the device-pointer API
     DBuf lits_scr, mu_scr, H_scr, table_scr, S64_scr, sat_scr, tmp;
     int32_t scr_Np = 0;
+    void* noalloc_scratch = nullptr; // this device's fixed scratch array (tsat_fwd_dev_noalloc)
+    int32_t noalloc_rc = 0;          // status of its address lookup at creation
 
     // graph replay of two iterations (one per buffer parity)
     bool use_graph = false;
@@ -464,6 +466,15 @@ int32_t tsat_create(const tsat_config* cfg, tsat_solver** out)
     if (hipSetDevice(dev) != hipSuccess) { delete s; return fail(TSAT_E_HIP, "hipSetDevice(%d) failed", dev); }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) s->cus = prop.multiProcessorCount;
+    // device address of the fixed scratch array, once per device (with it current)
+    {
+        const hipError_t e = noalloc_scratch_address(dev, &s->noalloc_scratch);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            s->noalloc_scratch = nullptr;
+            s->noalloc_rc = (int32_t)e;
+        }
+    }
     s->fwd_target_blocks = std::max(1, env_int("TSAT_FWD_TARGET_BLOCKS", s->fwd_target_blocks));
     s->var_per_cu = std::max(0, env_int("TSAT_VAR_BLOCKS_PER_CU", s->var_per_cu));
     s->pure_group = env_int("TSAT_PURE_GROUP", s->pure_group);
@@ -1386,6 +1397,69 @@ int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
     va.lits_cur = s->lits_scr.as<uint64_t>();
     va.U_out = U;
     HIPCHK(launch_var(va, VOP_ADJ, var_blocks(s, s->st.V), st));
+    return TSAT_OK;
+}
+
+int32_t tsat_fwd_dev_noalloc(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, float* S, uint32_t* hist,
+                             void* stream)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
+    if (N < 1 || N > TSAT_MAX_STEP_N || !bits || !(tau >= 0.f) || !std::isfinite(tau))
+        return fail(TSAT_E_ARG, "invalid arguments");
+    RET(need_single(s));
+    if (!s->noalloc_scratch) return fail(TSAT_E_HIP, "scratch array address unavailable (HIP error %d)", s->noalloc_rc);
+    RET(set_dev(s));
+    hipStream_t st = (hipStream_t)stream; // NULL: the null (default) stream
+    const int32_t W = (N + 63) / 64, Np = 64 * W, K1 = K1_of(s);
+    // layout: histogram accumulator [Np][K1] u32, then each bucket's units
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t h_bytes = up((size_t)Np * K1 * 4);
+    size_t need = h_bytes;
+    for (auto* b : s->buckets) {
+        if (b->count == 0 || b->k == 0) continue;
+        const FwdGeom g = fwd_geometry(N, K1, b->count, b->k, s->fwd_target_blocks);
+        const int64_t per = (int64_t)g.S * g.CPT;
+        need += up((size_t)((b->count + per - 1) / per) * sizeof(FwdUnit));
+    }
+    if (need > TSAT_NOALLOC_SCRATCH_BYTES)
+        return fail(TSAT_E_ARG, "needs %zu bytes of scratch, the fixed array holds %u", need, TSAT_NOALLOC_SCRATCH_BYTES);
+    uint8_t* base = static_cast<uint8_t*>(s->noalloc_scratch);
+    uint32_t* H = reinterpret_cast<uint32_t*>(base);
+    HIPCHK(launch_fill_u32(H, (int64_t)Np * K1, 0u, st));
+    size_t off = h_bytes;
+    for (auto* b : s->buckets) {
+        if (b->count == 0 || b->k == 0) continue;
+        const FwdGeom g = fwd_geometry(N, K1, b->count, b->k, s->fwd_target_blocks);
+        const int64_t per = (int64_t)g.S * g.CPT;
+        const int64_t nunits = (b->count + per - 1) / per;
+        FwdUnit* units = reinterpret_cast<FwdUnit*>(base + off);
+        off += up((size_t)nunits * sizeof(FwdUnit));
+        HIPCHK(launch_fwd_units(units, nunits, per, b->count, st));
+        FwdArgs a{};
+        a.units = units;
+        a.codes = b->codes.as<uint32_t>();
+        a.KW = b->k;
+        a.K1 = K1;
+        a.bits32 = reinterpret_cast<const uint32_t*>(bits);
+        a.W2 = 2 * W;
+        a.vrows = 1;
+        a.Dn = g.Dn;
+        a.DT = g.DT;
+        a.CPT = g.CPT;
+        a.H = H;
+        a.H_stride = (int64_t)Np * K1;
+        HIPCHK(launch_fwd(a, (int)nunits, g.tiles, st));
+    }
+    tsat_params p = s->params;
+    p.tau = tau;
+    SminArgs a = smin_args(s, p, N, Np);
+    a.H = H;
+    a.H_last = hist;
+    a.S_out = S;
+    a.update = 0;
+    HIPCHK(launch_smin(a, st));
     return TSAT_OK;
 }
 

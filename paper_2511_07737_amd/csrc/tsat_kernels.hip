@@ -18,7 +18,9 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
+#include "tsat.h"
 #include "tsat_device.h"
 #include "tsat_learned.h"
 
@@ -121,7 +123,16 @@ __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 // its bins to the global histogram.
 // ---------------------------------------------------------------------------
 
-template <int KW, int B>
+// Literal dword d of row `code` (2 var + neg).  VR: the rows hold the values
+// of the variables only ([V][W2] dwords); a negated literal is the complement.
+template <bool VR>
+__device__ __forceinline__ uint32_t lit_dword(const uint32_t* __restrict__ bits32, uint32_t code, int W2, int d)
+{
+    if (VR) return bits32[(size_t)(code >> 1) * W2 + d] ^ (0u - (code & 1u));
+    return bits32[(size_t)code * W2 + d];
+}
+
+template <int KW, int B, bool VR>
 __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
 {
     extern __shared__ uint32_t lh[]; // [DT*32][KW+1]
@@ -153,12 +164,12 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
                 const uint32_t code = a.codes[c * KW + q];
-                const uint32_t x = a.bits32[(size_t)code * a.W2 + d];
+                const uint32_t x = lit_dword<VR>(a.bits32, code, a.W2, d);
 #pragma unroll
                 for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x;
                 ge[0] |= x;
             }
-            if (KW >= 2 && KW <= 3 && a.planes) {
+            if (!VR && KW >= 2 && KW <= 3 && a.planes) {
                 // R in binary for the backward: bit 0 = parity of the
                 // cumulative masks, bit 1 = [R >= 2] (R <= 3)
                 uint32_t b0 = 0;
@@ -216,7 +227,7 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
 // the lane's own LDS bin R (no two lanes share a bin, so no conflicts); the
 // block then adds its four waves' bins into the global histogram.  Clauses
 // are taken G at a time, all their row loads issued before the first wait.
-template <int KMAX, int G>
+template <int KMAX, int G, bool VR>
 __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
 {
     extern __shared__ uint32_t lh[]; // [4 waves][64 lanes][K1]
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
                 x[g][q] = 0u;
                 if (q < k && c + g < ce) {
                     const uint32_t code = sload(a.codes + (c + g) * k + q);
-                    if (live) x[g][q] = a.bits32[(size_t)code * a.W2 + d];
+                    if (live) x[g][q] = lit_dword<VR>(a.bits32, code, a.W2, d);
                 }
             }
 #pragma unroll
@@ -2155,30 +2166,78 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a)
 // launchers (host side, same translation unit)
 // ---------------------------------------------------------------------------
 
-template <int KW, int B>
+template <int KW, int B, bool VR>
 static hipError_t launch_fwd_k(const FwdArgs& a, dim3 grid, hipStream_t st)
 {
     const size_t lds = (size_t)a.DT * 32 * (KW + 1) * sizeof(uint32_t);
-    hipLaunchKernelGGL((fwd_hist_kernel<KW, B>), grid, dim3(256), lds, st, a);
+    hipLaunchKernelGGL((fwd_hist_kernel<KW, B, VR>), grid, dim3(256), lds, st, a);
     return hipGetLastError();
+}
+
+template <bool VR>
+static hipError_t launch_fwd_vr(const FwdArgs& a, dim3 grid, hipStream_t st)
+{
+    switch (a.KW) {
+    case 1: return launch_fwd_k<1, 8, VR>(a, grid, st);
+    case 2: return launch_fwd_k<2, 8, VR>(a, grid, st);
+    case 3: return launch_fwd_k<3, 8, VR>(a, grid, st);
+    case 4: return launch_fwd_k<4, 8, VR>(a, grid, st);
+    default: {
+        const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
+        if (a.KW <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4, VR>), grid, dim3(256), lds, st, a);
+        else if (a.KW <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2, VR>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1, VR>), grid, dim3(256), lds, st, a);
+        return hipGetLastError();
+    }
+    }
 }
 
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st)
 {
     const dim3 grid((unsigned)nunits, (unsigned)tiles, 1);
-    switch (a.KW) {
-    case 1: return launch_fwd_k<1, 8>(a, grid, st);
-    case 2: return launch_fwd_k<2, 8>(a, grid, st);
-    case 3: return launch_fwd_k<3, 8>(a, grid, st);
-    case 4: return launch_fwd_k<4, 8>(a, grid, st);
-    default: {
-        const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
-        if (a.KW <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4>), grid, dim3(256), lds, st, a);
-        else if (a.KW <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2>), grid, dim3(256), lds, st, a);
-        else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1>), grid, dim3(256), lds, st, a);
-        return hipGetLastError();
+    return a.vrows ? launch_fwd_vr<true>(a, grid, st) : launch_fwd_vr<false>(a, grid, st);
+}
+
+// Work units of one single-instance bucket: unit j covers clauses
+// [j per, min((j + 1) per, Cb)).
+__global__ void fwd_units_kernel(FwdUnit* __restrict__ u, int64_t n, int64_t per, int64_t Cb)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    FwdUnit w;
+    w.inst = 0;
+    w.pad = 0;
+    w.c0 = j * per;
+    w.c1 = (j + 1) * per < Cb ? (j + 1) * per : Cb;
+    u[j] = w;
+}
+
+hipError_t launch_fwd_units(FwdUnit* u, int64_t n, int64_t per, int64_t Cb, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fwd_units_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, n, per, Cb);
+    return hipGetLastError();
+}
+
+// Fixed device memory of the allocation-free forward entry point.  In host
+// code the name stands for a host-side shadow: kernels get the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[TSAT_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_address(int device, void** out)
+{
+    static std::mutex mu;
+    static void* addr[64] = {};
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
     }
-    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_smin(const SminArgs& a, hipStream_t st)

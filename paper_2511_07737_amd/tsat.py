@@ -129,6 +129,7 @@ _SIGS = [
     ("tsat_get_grad", _i32, [_P, ct.POINTER(Params), _P, _P]),
     ("tsat_pack_dev", _i32, [_P, _P, _i32, _P, _P]),
     ("tsat_fwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
+    ("tsat_fwd_dev_noalloc", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_bwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_binarize_dev", _i32, [_P, _P, _i32, _i32, _P, _P, _P, _P]),
     ("tsat_get_adam_origin", _i32, [_P, _P]),
@@ -493,6 +494,10 @@ class Solver:
     def fwd_dev(self, bits_ptr: int, n: int, tau: float, S_ptr: int | None, hist_ptr: int | None,
                 stream: int | None = None) -> None:
         _check(lib().tsat_fwd_dev(self._h, bits_ptr, int(n), float(tau), S_ptr, hist_ptr, stream))
+
+    def fwd_dev_noalloc(self, bits_ptr: int, n: int, tau: float, S_ptr: int | None, hist_ptr: int | None,
+                        stream: int | None = None) -> None:
+        _check(lib().tsat_fwd_dev_noalloc(self._h, bits_ptr, int(n), float(tau), S_ptr, hist_ptr, stream))
 
     def bwd_dev(self, bits_ptr: int, n: int, tau: float, dS_ptr: int, U_ptr: int, stream: int | None = None) -> None:
         _check(lib().tsat_bwd_dev(self._h, bits_ptr, int(n), float(tau), dS_ptr, U_ptr, stream))
