@@ -26,7 +26,9 @@ def test_store_builder_under_sanitizers(tmp_path):
            os.path.join(CSRC, "tsat_store.cpp"), os.path.join(HERE, "store_check.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    env.pop("LD_PRELOAD", None)
+    # verify_asan_link_order=0: the sanitizer runtime need not be the first
+    # library the loader maps (the environment may preload others)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, env=env, timeout=240)
     assert r.returncode == 0 and "ALL OK" in r.stdout, r.stdout + r.stderr
