@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tsat.h"
 #include "tsat_types.h"
 
 namespace tsat {
@@ -71,9 +72,15 @@ struct FwdArgs {
     int64_t H_stride;       // Np * K1
     const Ctrl* ctrl;       // may be null
     const InstCtrl* ictrl;  // may be null
-    uint32_t* planes;       // null, or [Cb][2][plane_stride]: bits 0 and 1 of R per clause (widths 2, 3)
+    uint32_t* planes;       // null, or [clauses][plane_P][plane_stride]: R of every clause in binary
     int32_t plane_stride;   // dwords per plane row (2 J, J the update kernel's words per candidate row)
+    int32_t plane_P;        // planes per clause (2 or 4)
+    int64_t plane_base;     // global index of the bucket's first clause
     int32_t vrows;          // bits32 holds value rows only ([V][W2]); not-x is the complement
+    // KW = 0 (wide-clause kernel): the units of every wide bucket in one
+    // launch; a unit's width is in its pad field
+    const uint32_t* wide_codes[TSAT_MAX_WIDTH + 1];
+    int64_t wide_base[TSAT_MAX_WIDTH + 1];
 };
 
 struct SminArgs {
@@ -130,7 +137,9 @@ struct VarArgs {
     // then negative records holding the clause index (offsets as occ_off /
     // occ_mid), and the forward pass's planes of R for these bits
     const uint32_t* occ_cid;  // null: gather the other literals' rows instead
-    const uint32_t* planes;   // [Cb][2][2 J] dwords
+    const uint32_t* planes;   // [clauses][P][2 J] dwords
+    const uint32_t* cid_off;  // [V+1] record offsets of occ_cid
+    const uint32_t* cid_mid;  // [V] first record of negative occurrences
     // generic stores: variables with many occurrence words are split into
     // chunks of records handled by separate waves; their FP64 partial sums
     // are added in chunk order by one wave per variable, which runs the tail
@@ -155,6 +164,7 @@ struct SelectArgs {
 };
 
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st);
+hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st);
 hipError_t launch_smin(const SminArgs& a, hipStream_t st);
 hipError_t launch_fwd_units(FwdUnit* u, int64_t n, int64_t per, int64_t Cb, hipStream_t st);
 // device address of the allocation-free entry point's fixed scratch array on
@@ -167,6 +177,8 @@ hipError_t launch_pack(const float* assign, int V, int N, int W, uint64_t* out, 
 hipError_t launch_init_normal(float* theta, int64_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, int blocks, hipStream_t st);
+hipError_t launch_stream(int kind, uint32_t* a, uint32_t* b, uint32_t* c, const uint32_t* src, int64_t n4, int blocks,
+                         hipStream_t st);
 hipError_t launch_strided_rows(const uint64_t* src, int64_t rows, int w, int64_t src_stride, uint64_t* dst,
                                hipStream_t st);
 hipError_t launch_rank(const int64_t* sat, int N, int32_t* order, hipStream_t st);

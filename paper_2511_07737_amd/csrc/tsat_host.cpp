@@ -51,7 +51,8 @@ struct tsat_solver {
     Store st;
     std::vector<Bucket*> buckets;
     DBuf occ_off, occ_mid, occ_data, var_inst, info;
-    DBuf occ_cid;            // clause-index records (uniform widths 2, 3)
+    DBuf occ_cid;            // clause-index records (widths up to kMaxPlaneWidth)
+    DBuf cid_off, cid_mid;   // their record offsets (stores with generic occurrence records)
     DBuf planes, planes_scr; // R of every clause in binary, for the step / for evaluations
     DBuf heavy, hv_var, hv_chunk, ch_var, ch_beg, ch_end; // chunked heavy variables (generic stores)
     DBuf partial, partial_scr; // FP64 partial sums of the chunks, for the step / for evaluations
@@ -83,6 +84,9 @@ struct tsat_solver {
     int32_t clause_planes = 1;        // uniform widths 2, 3: backward gathers the forward's planes of R
     int32_t window_gather = 1;        // clause planes: 64 records per vector load, transposed across the wave
 
+    // forward work units of all wide buckets (widths > 4) in one launch, per clauses-per-wave
+    std::map<int, std::pair<DBuf*, int>> wide_units;
+
     // learned proposal: features and aggregation channels, kept proposal
     DBuf feat, fh[2], fzinv, prop;
     bool prop_valid = false;
@@ -103,6 +107,7 @@ struct tsat_solver {
     {
         drop_graph();
         for (auto* b : buckets) delete b;
+        for (auto& u : wide_units) delete u.second.first;
         for (auto e : events) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -190,14 +195,24 @@ static int32_t bucket_units(tsat_solver* s, Bucket* b, const FwdGeom& g, const F
 
 // Make every bucket's unit table for N candidates resident (before a graph
 // capture, which must not allocate or copy).
+static int32_t wide_geometry(const tsat_solver* s, int32_t N, FwdGeom* g, int* kmax);
+static int32_t wide_units(tsat_solver* s, const FwdGeom& g, const FwdUnit** out, int* count);
+
 static int32_t prepare_units(tsat_solver* s, int32_t N)
 {
     for (auto* b : s->buckets) {
-        if (b->count == 0 || b->k == 0) continue;
+        if (b->count == 0 || b->k == 0 || b->k > 4) continue;
         const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k, s->fwd_target_blocks);
         const FwdUnit* u;
         int n;
         RET(bucket_units(s, b, g, &u, &n));
+    }
+    FwdGeom g;
+    int kmax;
+    if (wide_geometry(s, N, &g, &kmax)) {
+        const FwdUnit* u;
+        int n;
+        RET(wide_units(s, g, &u, &n));
     }
     return TSAT_OK;
 }
@@ -206,20 +221,79 @@ static int32_t prepare_units(tsat_solver* s, int32_t N)
 // Words per candidate row the update kernels use for W words (a power of two).
 static int32_t row_words(int32_t W) { return W <= 2 ? W : (W <= 4 ? 4 : (W <= 8 ? 8 : 16)); }
 
-// The clause-plane update applies: uniform widths 2 or 3, at most 256 candidates.
-static bool plane_path(const tsat_solver* s, int32_t N)
+static bool uniform_plane_store(const tsat_solver* s) { return s->st.pure_k == 2 || s->st.pure_k == 3; }
+
+// LDS of the mixed-width window gather: four windows of P J 64 words and one
+// dL/dR table of K1 J 64 floats per block (one instance) or per wave (batch)
+static size_t levels_lds_bytes(const tsat_solver* s, int32_t J)
 {
-    return s->clause_planes && s->occ_cid.p && (N + 63) / 64 <= 4;
+    const size_t P = (size_t)planes_for_width(s->st.K);
+    return 4 * P * J * 64 * 8 + (s->st.n_inst > 1 ? 4 : 1) * (size_t)K1_of(s) * J * 64 * 4;
 }
 
-// Planes of R for N candidates: [Cb][2][2 J] dwords, zeroed when (re)allocated.
+// The clause-plane update applies: clause-index records exist (widths up to
+// kMaxPlaneWidth), at most 256 candidates, and, beyond uniform widths 2 and
+// 3 (which also have a record-by-record plane gather), the window gather
+// with its 16-bit counts and LDS budget.
+static bool plane_path(const tsat_solver* s, int32_t N)
+{
+    if (!s->clause_planes || !s->occ_cid.p || (N + 63) / 64 > 4) return false;
+    if (uniform_plane_store(s)) return true;
+    return s->window_gather && s->st.max_sign_rec < 65536 && levels_lds_bytes(s, row_words((N + 63) / 64)) <= 65536;
+}
+
+// Planes of R for N candidates: [clauses][P][2 J] dwords, zeroed when (re)allocated.
 static int32_t ensure_planes(tsat_solver* s, DBuf& buf, int32_t N, hipStream_t st)
 {
-    const size_t Cb = (size_t)s->st.width_count[s->st.pure_k];
-    const size_t bytes = std::max<size_t>(16, Cb * 16 * (size_t)row_words((N + 63) / 64));
+    const size_t P = (size_t)planes_for_width(s->st.K);
+    const size_t bytes = std::max<size_t>(16, (size_t)s->st.plane_clauses * P * 8 * (size_t)row_words((N + 63) / 64));
     if (buf.p && buf.bytes >= bytes) return TSAT_OK;
     RET(buf.alloc(bytes, "clause planes"));
     HIPCHK(launch_fill_u32(buf.as<uint32_t>(), (int64_t)(bytes / 4), 0u, st));
+    return TSAT_OK;
+}
+
+// Work units of every wide bucket (width > 4) for one launch of the
+// wide-clause kernel: per bucket and instance, ranges of 4 CPT clauses
+// (a unit never spans two buckets or instances); the width goes in pad.
+static int32_t wide_geometry(const tsat_solver* s, int32_t N, FwdGeom* g, int* kmax)
+{
+    int64_t Cw = 0;
+    *kmax = 0;
+    for (auto* b : s->buckets)
+        if (b->k > 4 && b->count > 0) {
+            Cw += b->count;
+            *kmax = std::max(*kmax, b->k);
+        }
+    *g = fwd_geometry(N, K1_of(s), Cw, 5, s->fwd_target_blocks);
+    return Cw > 0;
+}
+
+static int32_t wide_units(tsat_solver* s, const FwdGeom& g, const FwdUnit** out, int* count)
+{
+    auto it = s->wide_units.find(g.CPT);
+    if (it == s->wide_units.end()) {
+        std::vector<FwdUnit> u;
+        const int64_t per = (int64_t)g.S * g.CPT;
+        for (auto* b : s->buckets) {
+            if (b->k <= 4 || b->count == 0) continue;
+            const auto& off = s->st.inst_off[b->k];
+            for (int32_t j = 0; j < s->st.n_inst; ++j)
+                for (int64_t c = off[j]; c < off[j + 1]; c += per)
+                    u.push_back(FwdUnit{j, b->k, c, std::min(c + per, off[j + 1])});
+        }
+        DBuf* d = new (std::nothrow) DBuf();
+        if (!d) return fail(TSAT_E_OOM, "host allocation failed");
+        int32_t rc = d->alloc(std::max<size_t>(1, u.size()) * sizeof(FwdUnit), "forward units");
+        if (rc) { delete d; return rc; }
+        if (!u.empty()) {
+            hipError_t e = hipMemcpy(d->p, u.data(), u.size() * sizeof(FwdUnit), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { delete d; return fail(TSAT_E_HIP, "unit upload: %s", hipGetErrorString(e)); }
+        }
+        it = s->wide_units.emplace(g.CPT, std::make_pair(d, (int)u.size())).first;
+    }
+    *out = it->second.first->as<FwdUnit>();
+    *count = it->second.second;
     return TSAT_OK;
 }
 
@@ -227,30 +301,53 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
                            const InstCtrl* ictrl, hipStream_t st, uint32_t* planes = nullptr)
 {
     const int32_t W = (N + 63) / 64;
+    const bool with_planes = planes && plane_path(s, N);
+    FwdArgs base{};
+    base.K1 = K1_of(s);
+    base.bits32 = reinterpret_cast<const uint32_t*>(lits);
+    base.W2 = 2 * W;
+    base.H = H;
+    base.H_stride = (int64_t)64 * W * base.K1;
+    base.ctrl = ctrl;
+    base.ictrl = ictrl;
+    if (with_planes) {
+        base.planes = planes;
+        base.plane_stride = 2 * row_words(W);
+        base.plane_P = planes_for_width(s->st.K);
+    }
+    // widths 1 .. 4: one launch per bucket
     for (auto* b : s->buckets) {
-        if (b->count == 0 || b->k == 0) continue;
+        if (b->count == 0 || b->k == 0 || b->k > 4) continue;
         const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k, s->fwd_target_blocks);
-        FwdArgs a{};
+        FwdArgs a = base;
         int nunits = 0;
         RET(bucket_units(s, b, g, &a.units, &nunits));
         if (nunits == 0) continue;
         a.codes = b->codes.as<uint32_t>();
         a.KW = b->k;
-        a.K1 = K1_of(s);
-        a.bits32 = reinterpret_cast<const uint32_t*>(lits);
-        a.W2 = 2 * W;
         a.Dn = g.Dn;
         a.DT = g.DT;
         a.CPT = g.CPT;
-        a.H = H;
-        a.H_stride = (int64_t)64 * W * a.K1;
-        a.ctrl = ctrl;
-        a.ictrl = ictrl;
-        if (planes && plane_path(s, N) && b->k == s->st.pure_k) {
-            a.planes = planes;
-            a.plane_stride = 2 * row_words(W);
-        }
+        if (with_planes) a.plane_base = s->st.plane_base[b->k];
         HIPCHK(launch_fwd(a, nunits, g.tiles, st));
+    }
+    // wider clauses: every bucket in one launch
+    FwdGeom g;
+    int kmax = 0;
+    if (wide_geometry(s, N, &g, &kmax)) {
+        FwdArgs a = base;
+        int nunits = 0;
+        RET(wide_units(s, g, &a.units, &nunits));
+        a.KW = 0;
+        a.Dn = g.Dn;
+        a.DT = g.DT;
+        a.CPT = g.CPT;
+        for (auto* b : s->buckets) {
+            if (b->k <= 4 || b->count == 0) continue;
+            a.wide_codes[b->k] = b->codes.as<uint32_t>();
+            if (with_planes) a.wide_base[b->k] = s->st.plane_base[b->k];
+        }
+        if (nunits > 0) HIPCHK(launch_fwd_wide(a, kmax, nunits, g.tiles, st));
     }
     return TSAT_OK;
 }
@@ -301,7 +398,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.pure_k = s->st.pure_k;
     a.group = s->pure_group;
     // the window gather keeps its counts in 16-bit halves
-    a.window = s->window_gather && s->st.max_sign_deg < 65536;
+    a.window = s->window_gather && s->st.max_sign_rec < 65536;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
     a.occ_data = s->occ_data.as<uint32_t>();
@@ -314,6 +411,8 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     // clause-plane gather: evaluations write their planes to planes_scr, the
     // step overrides this with its own buffer
     a.occ_cid = plane_path(s, N) ? s->occ_cid.as<uint32_t>() : nullptr;
+    a.cid_off = s->cid_off.p ? s->cid_off.as<uint32_t>() : a.occ_off;
+    a.cid_mid = s->cid_mid.p ? s->cid_mid.as<uint32_t>() : a.occ_mid;
     a.planes = s->planes_scr.as<uint32_t>();
     if (s->heavy.p) {
         a.heavy = s->heavy.as<uint32_t>();
@@ -516,6 +615,8 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     s->drop_graph();
     for (auto* b : s->buckets) delete b;
     s->buckets.clear();
+    for (auto& u : s->wide_units) delete u.second.first;
+    s->wide_units.clear();
     s->loaded = false;
     s->N = s->W = s->Np = 0;
     s->scr_Np = 0;
@@ -550,6 +651,14 @@ static int32_t load_store(tsat_solver* s, Store&& st)
         RET(s->occ_cid.alloc((nr + 64) * 4, "clause-index records"));
         HIPCHK(launch_fill_u32(s->occ_cid.as<uint32_t>() + nr, 64, 0u, s->stream));
         HIPCHK(hipMemcpy(s->occ_cid.p, s->st.occ_cid.data(), nr * 4, hipMemcpyHostToDevice));
+    }
+    s->cid_off.release();
+    s->cid_mid.release();
+    if (!s->st.cid_off.empty()) {
+        RET(s->cid_off.alloc((V + 1) * 4, "clause-index record offsets"));
+        RET(s->cid_mid.alloc(std::max<size_t>(1, V) * 4, "clause-index record offsets"));
+        HIPCHK(hipMemcpy(s->cid_off.p, s->st.cid_off.data(), (V + 1) * 4, hipMemcpyHostToDevice));
+        if (V) HIPCHK(hipMemcpy(s->cid_mid.p, s->st.cid_mid.data(), V * 4, hipMemcpyHostToDevice));
     }
     s->planes.release();
     s->planes_scr.release();
@@ -1667,7 +1776,7 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
     // planes, so the shapes are compared on forward + update time
     for (int cp = planes_apply ? 1 : 0; cp >= 0; --cp) {
         const int ngroups = (pure && !cp) ? 3 : 1;
-        const int nwin = cp ? 2 : 1;
+        const int nwin = (cp && uniform_plane_store(s)) ? 2 : 1;
         for (int pc : kPerCu) {
             for (int gi = 0; gi < ngroups; ++gi) {
                 for (int wi = 0; wi < nwin; ++wi) {
@@ -1675,7 +1784,7 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
                     c.var_blocks_per_cu = pc;
                     c.pure_group = ngroups > 1 ? kGroups[gi] : cur.pure_group;
                     c.clause_planes = planes_apply ? cp : cur.clause_planes;
-                    c.window_gather = nwin > 1 ? 1 - wi : cur.window_gather;
+                    c.window_gather = nwin > 1 ? 1 - wi : (cp ? 1 : cur.window_gather);
                     RET(tsat_set_launch_config(s, &c));
                     RET(time_iterations(s, iters, p, ms));
                     used += iters;
@@ -1743,6 +1852,53 @@ int32_t tsat_copy_calibrate(tsat_solver* s, int64_t bytes, double* ms)
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return fail(TSAT_E_HIP, "copy kernel failed: %s", hipGetErrorString(err));
     if (ms) *ms = t;
+    return TSAT_OK;
+}
+
+int32_t tsat_stream_calibrate(tsat_solver* s, int64_t bytes, int32_t kind, int32_t reps, double* ms)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (bytes < 16384 || bytes % 16384) return fail(TSAT_E_ARG, "bytes must be a positive multiple of 16384");
+    if (kind < 0 || kind > 2) return fail(TSAT_E_ARG, "kind must be 0, 1 or 2");
+    if (reps < 1 || reps > 1000) return fail(TSAT_E_ARG, "reps must be in [1, 1000]");
+    RET(set_dev(s));
+    DBuf a, b, c, src;
+    RET(a.alloc((size_t)bytes, "stream array"));
+    if (kind == 0) {
+        RET(src.alloc((size_t)bytes, "stream source"));
+        HIPCHK(launch_fill_u32(src.as<uint32_t>(), bytes / 4, 1u, s->stream));
+    } else {
+        RET(b.alloc((size_t)bytes, "stream array"));
+        RET(c.alloc((size_t)bytes, "stream array"));
+        HIPCHK(launch_fill_u32(b.as<uint32_t>(), bytes / 4, 2u, s->stream));
+        HIPCHK(launch_fill_u32(c.as<uint32_t>(), bytes / 4, 3u, s->stream));
+    }
+    HIPCHK(launch_fill_u32(a.as<uint32_t>(), bytes / 4, 1u, s->stream));
+    const int64_t n4 = bytes / 16;
+    // every block a few passes over its share: 8 blocks per CU
+    const int blocks = 8 * s->cus;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(TSAT_E_HIP, "hipEventCreate failed");
+    }
+    // one untimed launch, then reps timed ones
+    hipError_t err = launch_stream(kind, a.as<uint32_t>(), b.as<uint32_t>(), c.as<uint32_t>(), src.as<uint32_t>(), n4,
+                                   blocks, s->stream);
+    if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
+    for (int32_t r = 0; r < reps && err == hipSuccess; ++r)
+        err = launch_stream(kind, a.as<uint32_t>(), b.as<uint32_t>(), c.as<uint32_t>(), src.as<uint32_t>(), n4, blocks,
+                            s->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(TSAT_E_HIP, "stream kernel failed: %s", hipGetErrorString(err));
+    if (ms) *ms = t / reps;
     return TSAT_OK;
 }
 

@@ -169,15 +169,18 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
                 for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x;
                 ge[0] |= x;
             }
-            if (!VR && KW >= 2 && KW <= 3 && a.planes) {
-                // R in binary for the backward: bit 0 = parity of the
-                // cumulative masks, bit 1 = [R >= 2] (R <= 3)
-                uint32_t b0 = 0;
+            if (!VR && a.planes) {
+                // R in binary for the backward, plane_P planes: bit p of R is
+                // the parity of the masks [R >= m 2^p], m >= 1
+                uint32_t* P = a.planes + (size_t)(a.plane_base + c) * (size_t)(a.plane_P * a.plane_stride) + d;
 #pragma unroll
-                for (int r = 0; r < KW; ++r) b0 ^= ge[r];
-                uint32_t* P = a.planes + (size_t)c * (2 * a.plane_stride);
-                P[d] = b0;
-                P[a.plane_stride + d] = ge[KW >= 2 ? 1 : 0];
+                for (int p = 0; p < 4; ++p) {
+                    if (p >= a.plane_P) break;
+                    uint32_t bp = 0;
+#pragma unroll
+                    for (int r = 1 << p; r <= KW; r += 1 << p) bp ^= ge[r - 1];
+                    P[(size_t)p * a.plane_stride] = bp;
+                }
             }
 #pragma unroll
             for (int r = 0; r < KW; ++r) {
@@ -236,7 +239,10 @@ __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
     if (a.ictrl && a.ictrl[u.inst].frozen) return;
     uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
     const uint32_t lane = __lane_id(), wave = threadIdx.x / 64u;
-    const int K1 = a.K1, k = a.KW;
+    // KW = 0: the units of every wide bucket in one launch, unit width in pad
+    const int K1 = a.K1, k = a.KW > 0 ? a.KW : u.pad;
+    const uint32_t* codes = a.KW > 0 ? a.codes : a.wide_codes[k];
+    const int64_t pbase = a.KW > 0 ? a.plane_base : a.wide_base[k];
     const uint32_t cand = blockIdx.y * 64u + lane;
     const uint32_t d = cand >> 5, bit = cand & 31u;
     const bool live = (int)d < a.Dn;
@@ -253,7 +259,7 @@ __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
             for (int q = 0; q < KMAX; ++q) {
                 x[g][q] = 0u;
                 if (q < k && c + g < ce) {
-                    const uint32_t code = sload(a.codes + (c + g) * k + q);
+                    const uint32_t code = sload(codes + (c + g) * k + q);
                     if (live) x[g][q] = lit_dword<VR>(a.bits32, code, a.W2, d);
                 }
             }
@@ -264,6 +270,19 @@ __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
 #pragma unroll
             for (int q = 0; q < KMAX; ++q) R += (x[g][q] >> bit) & 1u;
             if (live) atomicAdd(&my[R], 1u);
+            if (!VR && a.planes) {
+                // R in binary for the backward: plane p of this clause, word
+                // blockIdx.y (the wave's 64 candidates), one bit per lane
+                uint64_t bal[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) bal[p] = ballot64((R >> p) & 1u);
+                if (lane == 0) {
+                    uint64_t* P = (uint64_t*)a.planes + (size_t)(pbase + c + g) * (size_t)(a.plane_P * a.plane_stride / 2) + blockIdx.y;
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+                        if (p < a.plane_P) P[(size_t)p * (a.plane_stride / 2)] = bal[p];
+                }
+            }
         }
     }
     __syncthreads();
@@ -1886,6 +1905,186 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Clause-plane update by record windows for mixed widths (and uniform widths
+// 1 and 4 .. 15).
+//
+// The forward leaves R of every clause in binary in P planes (P = 2 up to
+// width 3, else 4), at the clause's global index.  A record is that index.
+// As in var_window_kernel a wave takes a chunk of consecutive variables and
+// their records 64 at a time: each lane loads one record's P J plane words,
+// every word is transposed across the wave into the wave's LDS window, and
+// a variable counts, per level r = 1 .. KT and candidate, its positive and
+// negative records whose clause has R >= r (the comparison of the P-bit R
+// with the constant r, bit-sliced over 64 records, then two popcounts).
+// U_vi = sum over r of (positive - negative records with R = r) dL/dR_i[r]
+// (Sec. III-B: P^T dL/dR with the straight-through estimator), formed from
+// these exact counts in the order of r; the tail is the one shared with the
+// other update kernels.  A single-instance solver keeps one dL/dR table per
+// block, a batch one per wave (the instance at hand).
+// ---------------------------------------------------------------------------
+
+// [R >= r] for the constant r, bit-sliced: R = sum_p 2^p planes[p].  From the
+// lowest bit up, t = [R restricted to bits < p >= r restricted to bits < p];
+// bit p of r set: t = plane_p & t, clear: t = plane_p | t.
+template <int P, int R>
+__device__ __forceinline__ uint64_t level_ge(const uint64_t (&pl)[P])
+{
+    uint64_t t = ~0ull;
+#pragma unroll
+    for (int p = 0; p < P; ++p) t = ((R >> p) & 1) ? (pl[p] & t) : (pl[p] | t);
+    if constexpr ((R >> P) != 0) t = 0ull; // r beyond what P bits hold
+    return t;
+}
+
+template <int P, int KT, int R = 1>
+__device__ __forceinline__ void count_levels(const uint64_t (&pl)[P], uint64_t mp, uint64_t mn, uint32_t (&cnt)[KT])
+{
+    if constexpr (R <= KT) {
+        const uint64_t t = level_ge<P, R>(pl);
+        cnt[R - 1] += (uint32_t)__popcll(t & mp) + ((uint32_t)__popcll(t & mn) << 16);
+        count_levels<P, KT, R + 1>(pl, mp, mn, cnt);
+    }
+}
+
+// Planes of records [w, w + 64) (records at or past `end` read as zero),
+// transposed into the wave's window: win[(p J + j) 64 + lane] bit r = plane
+// p, word j, candidate bit of record w + r.  Lane-private slots.
+template <int J, int P>
+__device__ __forceinline__ void load_window_p(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane, uint64_t* win)
+{
+    constexpr int Q = P * J / 2; // 16-byte loads per record (P even)
+    const uint32_t rec = w + lane;
+    const bool ok = rec < end;
+    const uint32_t id = ok ? a.occ_cid[rec] : 0u;
+    const uint4* pl = (const uint4*)a.planes + (size_t)id * Q;
+    uint64_t wd[P * J];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const uint4 q = ok ? pl[k] : make_uint4(0u, 0u, 0u, 0u);
+        wd[2 * k] = ((uint64_t)q.y << 32) | q.x;
+        wd[2 * k + 1] = ((uint64_t)q.w << 32) | q.z;
+    }
+#pragma unroll
+    for (int e = 0; e < P * J; ++e) win[e * 64 + lane] = transpose64(wd[e], lane);
+}
+
+template <int J, int KT, int OP>
+__global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
+{
+    if (OP == OP_STEP && a.ctrl->stop) {
+        copy_bits_on_stop(a);
+        return;
+    }
+    if (OP == OP_STEP && a.ctrl->mixing) {
+        mix_rows<J>(a);
+        return;
+    }
+    constexpr int P = KT <= 3 ? 2 : 4;
+    constexpr uint32_t kChunk = 4; // variables per wave work item
+    const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
+    const uint32_t wave0 = uniform(blockIdx.x * 4u + wv);
+    const uint32_t nwaves = uniform(gridDim.x * 4u);
+    const uint32_t V = (uint32_t)a.V;
+    const int W = a.W, K1 = a.K1, Np = a.Np;
+    const StepScalars c = load_scalars(a, OP);
+    // dynamic LDS: [4][P J 64] u64 windows, then the dL/dR table(s)
+    // [K1][J][64] f32, one per block (single instance) or one per wave
+    extern __shared__ uint64_t lds_lv[];
+    uint64_t* my_win = lds_lv + (size_t)wv * (P * J * 64);
+    float* gt_base = (float*)(lds_lv + 4 * P * J * 64);
+    const bool per_wave = a.var_inst != nullptr;
+    float* my_gt = gt_base + (per_wave ? (size_t)wv * K1 * J * 64 : 0);
+    uint32_t gt_inst = 0xffffffffu;
+    if (!per_wave) {
+        for (int e = threadIdx.x; e < K1 * J * 64; e += 256) {
+            const int r = e / (J * 64), j = (e / 64) % J, l = e % 64;
+            my_gt[e] = (j < W) ? a.tbl[(size_t)r * Np + 64 * j + l] : 0.f;
+        }
+        __syncthreads();
+        gt_inst = 0;
+    }
+    int bad = 0;
+    const uint32_t nchunks = (V + kChunk - 1) / kChunk;
+
+    for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
+        const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
+        const uint32_t rend = sload(a.cid_off + ve);
+        uint32_t w = 0;
+        bool loaded = false;
+        for (uint32_t v = vb; v < ve; ++v) {
+            const VarInst vi = var_instance<OP>(a, v);
+            if (vi.frozen) {
+                keep_variable<J>(a, v, lane);
+                continue;
+            }
+            if (vi.inst != gt_inst) { // per-wave tables only
+                gt_inst = vi.inst;
+                const float* tg = a.tbl + (size_t)vi.inst * K1 * Np;
+                for (int r = 0; r < K1; ++r)
+#pragma unroll
+                    for (int j = 0; j < J; ++j) my_gt[(r * J + j) * 64 + lane] = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
+            }
+            const uint32_t r0 = sload(a.cid_off + v), rm = sload(a.cid_mid + v), r1 = sload(a.cid_off + v + 1);
+            // per level r and word j: positive records with R >= r in the low
+            // 16 bits, negative in the high (the host keeps every variable
+            // below 2^16 records per sign on this path)
+            uint32_t cnt[J][KT];
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+#pragma unroll
+                for (int r = 0; r < KT; ++r) cnt[j][r] = 0;
+            for (uint32_t q = r0; q < r1;) { // wave-uniform
+                if (!loaded || q - w >= 64u) {
+                    w = q;
+                    loaded = true;
+                    load_window_p<J, P>(a, w, rend, lane, my_win);
+                }
+                const uint32_t hi = r1 < w + 64u ? r1 : w + 64u;
+                const uint64_t mp = q < rm ? bit_range(q - w, (hi < rm ? hi : rm) - w) : 0ull;
+                const uint64_t mn = hi > rm ? bit_range((q > rm ? q : rm) - w, hi - w) : 0ull;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    uint64_t pl[P];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) pl[p] = my_win[(p * J + j) * 64 + lane];
+                    count_levels<P, KT>(pl, mp, mn, cnt[j]);
+                }
+                q = hi;
+            }
+            float th[J], mm[J], vv[J];
+            bool valid[J];
+            load_row<J, OP, false>(a, v, lane, th, mm, vv, valid);
+            bool clamped = false;
+            const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
+            const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+            uint64_t oP[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
+            // U = sum over r of (positive - negative records with R = r) dL/dR[r]
+            const uint32_t total = (rm - r0) | ((r1 - rm) << 16);
+            double U[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                float u = 0.f;
+#pragma unroll
+                for (int r = 0; r <= KT; ++r) {
+                    if (r >= K1) break; // no clause is wider than the store's widest
+                    const uint32_t e = (r == 0 ? total : cnt[j][r - 1]) - (r < KT ? cnt[j][r] : 0u);
+                    const int32_t d = (int32_t)(e & 0xffffu) - (int32_t)(e >> 16);
+                    u = fmaf((float)d, my_gt[(r * J + j) * 64 + lane], u);
+                }
+                U[j] = (double)u;
+            }
+            var_tail<J, OP>(a, c, v, lane, th, mm, vv, valid, mu, clamped, U, oP, vi.witness, vi.wcand, bad);
+        }
+    }
+    if (OP == OP_STEP) {
+        if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
+        advance_step(a);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
 
@@ -2013,6 +2212,94 @@ __global__ void copy16_kernel(uint4* __restrict__ dst, const uint4* __restrict__
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) dst[e] = src[e];
+}
+
+// Bandwidth reference kernels (calibration of the roofline): streams with
+// 16-byte non-temporal accesses, four loads per array in flight per thread
+// (KIND 0: copy src -> a; KIND 1: three arrays read and written in place,
+// the pattern of the optimizer state), or with the update kernels' own
+// access pattern (KIND 2: three arrays in place, rows of 256 floats, one
+// dword per lane and load, four loads per array in flight).
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+
+template <int KIND>
+__global__ __launch_bounds__(256) void stream_kernel(uint32_t* __restrict__ a, uint32_t* __restrict__ b,
+                                                      uint32_t* __restrict__ c, const uint32_t* __restrict__ src,
+                                                      int64_t n4)
+{
+    const int64_t tiles = (n4 + 1023) / 1024; // 1024 16-byte units per block pass
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        if (KIND == 2) {
+            // each wave: four rows of 256 dwords of each array (one 1 KiB row
+            // = one 16-byte unit per lane); lane l takes dwords 64 j + l
+            const int64_t row0 = t * 16 + (threadIdx.x / 64) * 4;
+            const uint32_t l = __lane_id();
+            uint32_t x[4][4], y[4][4], z[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = (row0 + r) * 256 + 64 * j + l;
+                    const bool ok = e < 4 * n4;
+                    x[r][j] = ok ? __builtin_nontemporal_load(a + e) : 0u;
+                    y[r][j] = ok ? __builtin_nontemporal_load(b + e) : 0u;
+                    z[r][j] = ok ? __builtin_nontemporal_load(c + e) : 0u;
+                }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = (row0 + r) * 256 + 64 * j + l;
+                    if (e >= 4 * n4) continue;
+                    __builtin_nontemporal_store(x[r][j] ^ y[r][j], a + e);
+                    __builtin_nontemporal_store(y[r][j] + z[r][j], b + e);
+                    __builtin_nontemporal_store(z[r][j] ^ x[r][j], c + e);
+                }
+            continue;
+        }
+        v4u32* A = (v4u32*)a;
+        v4u32* B = (v4u32*)b;
+        v4u32* Cc = (v4u32*)c;
+        const v4u32* S = (const v4u32*)src;
+        v4u32 x[4], y[4], z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t e = t * 1024 + k * 256 + threadIdx.x;
+            const bool ok = e < n4;
+            const v4u32 zero = {0u, 0u, 0u, 0u};
+            if (KIND == 0) {
+                x[k] = ok ? __builtin_nontemporal_load(S + e) : zero;
+            } else {
+                x[k] = ok ? __builtin_nontemporal_load(A + e) : zero;
+                y[k] = ok ? __builtin_nontemporal_load(B + e) : zero;
+                z[k] = ok ? __builtin_nontemporal_load(Cc + e) : zero;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t e = t * 1024 + k * 256 + threadIdx.x;
+            if (e >= n4) continue;
+            if (KIND == 0) {
+                __builtin_nontemporal_store(x[k], A + e);
+            } else {
+                __builtin_nontemporal_store(x[k] ^ y[k], A + e);
+                __builtin_nontemporal_store(y[k] + z[k], B + e);
+                __builtin_nontemporal_store(z[k] ^ x[k], Cc + e);
+            }
+        }
+    }
+}
+
+hipError_t launch_stream(int kind, uint32_t* a, uint32_t* b, uint32_t* c, const uint32_t* src, int64_t n4, int blocks,
+                         hipStream_t st)
+{
+    if (n4 <= 0) return hipSuccess;
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(stream_kernel<0>, dim3(blocks), dim3(256), 0, st, a, b, c, src, n4); break;
+    case 1: hipLaunchKernelGGL(stream_kernel<1>, dim3(blocks), dim3(256), 0, st, a, b, c, src, n4); break;
+    default: hipLaunchKernelGGL(stream_kernel<2>, dim3(blocks), dim3(256), 0, st, a, b, c, src, n4); break;
+    }
+    return hipGetLastError();
 }
 
 // dst[r][j] = src[r * src_stride + j] for r < rows, j < w (64-bit words):
@@ -2190,6 +2477,17 @@ static hipError_t launch_fwd_vr(const FwdArgs& a, dim3 grid, hipStream_t st)
         return hipGetLastError();
     }
     }
+}
+
+// every wide bucket (widths 5 .. kmax) in one launch: a.KW = 0, unit widths in pad
+hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st)
+{
+    const dim3 grid((unsigned)nunits, (unsigned)tiles, 1);
+    const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
+    if (kmax <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4, false>), grid, dim3(256), lds, st, a);
+    else if (kmax <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2, false>), grid, dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1, false>), grid, dim3(256), lds, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st)
@@ -2400,14 +2698,70 @@ static hipError_t launch_plane_j(const VarArgs& a, int op, int blocks, hipStream
     return full ? launch_plane_jkf<J, 3, true>(a, op, blocks, st) : launch_plane_jkf<J, 3, false>(a, op, blocks, st);
 }
 
+// mixed-width window gather: levels KT >= the widest clause (K1 - 1)
+static int levels_of(const VarArgs& a)
+{
+    const int K = a.K1 - 1;
+    return K <= 3 ? 3 : (K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 12 ? 12 : 15)));
+}
+
+static size_t levels_lds(const VarArgs& a, int J, int KT)
+{
+    const size_t P = KT <= 3 ? 2 : 4;
+    return 4 * P * J * 64 * 8 + (a.var_inst ? 4 : 1) * (size_t)a.K1 * J * 64 * 4;
+}
+
+template <int J, int KT>
+static auto levels_kernel_ptr(int op)
+{
+    return op == OP_STEP ? var_window_levels_kernel<J, KT, OP_STEP>
+                         : (op == OP_GRAD ? var_window_levels_kernel<J, KT, OP_GRAD> : var_window_levels_kernel<J, KT, OP_ADJ>);
+}
+
+template <int J>
+static hipError_t launch_levels_j(const VarArgs& a, int op, int blocks, hipStream_t st)
+{
+    const int KT = levels_of(a);
+    const size_t lds = levels_lds(a, J, KT);
+    switch (KT) {
+    case 3: hipLaunchKernelGGL((levels_kernel_ptr<J, 3>(op)), dim3(blocks), dim3(256), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((levels_kernel_ptr<J, 4>(op)), dim3(blocks), dim3(256), lds, st, a); break;
+    case 8: hipLaunchKernelGGL((levels_kernel_ptr<J, 8>(op)), dim3(blocks), dim3(256), lds, st, a); break;
+    case 12: hipLaunchKernelGGL((levels_kernel_ptr<J, 12>(op)), dim3(blocks), dim3(256), lds, st, a); break;
+    default: hipLaunchKernelGGL((levels_kernel_ptr<J, 15>(op)), dim3(blocks), dim3(256), lds, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int J>
+static int occupancy_levels_j(const VarArgs& a)
+{
+    const int KT = levels_of(a);
+    const size_t lds = levels_lds(a, J, KT);
+    switch (KT) {
+    case 3: return occupancy_of(levels_kernel_ptr<J, 3>(OP_STEP), lds);
+    case 4: return occupancy_of(levels_kernel_ptr<J, 4>(OP_STEP), lds);
+    case 8: return occupancy_of(levels_kernel_ptr<J, 8>(OP_STEP), lds);
+    case 12: return occupancy_of(levels_kernel_ptr<J, 12>(OP_STEP), lds);
+    default: return occupancy_of(levels_kernel_ptr<J, 15>(OP_STEP), lds);
+    }
+}
+
 hipError_t launch_var(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
     const bool rowwise = op == OP_BINARIZE || op == OP_NORMBWD; // no gather
-    if (a.occ_cid && a.planes && !rowwise && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
+    if (a.occ_cid && a.planes && !rowwise && a.W <= 4) {
+        if (a.pure_k == 2 || a.pure_k == 3) {
+            switch (a.W) {
+            case 1: return launch_plane_j<1>(a, op, blocks, st);
+            case 2: return launch_plane_j<2>(a, op, blocks, st);
+            default: return launch_plane_j<4>(a, op, blocks, st);
+            }
+        }
         switch (a.W) {
-        case 1: return launch_plane_j<1>(a, op, blocks, st);
-        case 2: return launch_plane_j<2>(a, op, blocks, st);
-        default: return launch_plane_j<4>(a, op, blocks, st);
+        case 1: return launch_levels_j<1>(a, op, blocks, st);
+        case 2: return launch_levels_j<2>(a, op, blocks, st);
+        default: return launch_levels_j<4>(a, op, blocks, st);
         }
     }
     const bool pure = a.pure_k >= 2 && a.pure_k <= 4 && !rowwise;
@@ -2447,6 +2801,13 @@ static int occupancy_j(const VarArgs& a, bool pure)
 int var_occupancy(const VarArgs& a, int op)
 {
     const bool rowwise = op == OP_BINARIZE || op == OP_NORMBWD; // no gather
+    if (a.occ_cid && a.planes && !rowwise && a.pure_k != 2 && a.pure_k != 3 && a.W <= 4) {
+        switch (a.W) {
+        case 1: return occupancy_levels_j<1>(a);
+        case 2: return occupancy_levels_j<2>(a);
+        default: return occupancy_levels_j<4>(a);
+        }
+    }
     if (a.occ_cid && a.planes && !rowwise && (a.pure_k == 2 || a.pure_k == 3) && a.W <= 4) {
         const bool k2 = a.pure_k == 2, win = a.window != 0;
         if (pair_rows(a))

@@ -158,8 +158,6 @@ int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_t* lit_
         if (words > lim.max_occ_words)
             return fail(TSAT_E_ARG, "occurrence store exceeds %llu words", (unsigned long long)lim.max_occ_words);
         st.occ_data.assign(words, 0);
-        const bool cid = pure && (st.pure_k == 2 || st.pure_k == 3);
-        if (cid) st.occ_cid.assign(total, 0);
         std::vector<uint32_t> curp(V), curn(V);
         for (int32_t v = 0; v < V; ++v) {
             curp[v] = st.occ_off[v];
@@ -177,7 +175,6 @@ int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_t* lit_
                         size_t w = (size_t)pos * (size_t)(k - 1);
                         for (int f = 0; f < k; ++f)
                             if (f != e) st.occ_data[w++] = lit[f];
-                        if (cid) st.occ_cid[pos] = (uint32_t)c;
                         ++pos;
                     } else {
                         st.occ_data[pos++] = (uint32_t)(k - 1);
@@ -218,6 +215,51 @@ int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_t* lit_
         }
     } catch (const std::bad_alloc&) {
         return fail(TSAT_E_OOM, "host allocation failed while building the occurrence store");
+    }
+    // clause-index records for the plane gathers
+    if (st.K >= 1 && st.K <= kMaxPlaneWidth && (uint64_t)st.L < 0xffffffffull && (uint64_t)st.C < 0xffffffffull) {
+        try {
+            st.plane_base.assign(TSAT_MAX_WIDTH + 1, 0);
+            int64_t base = 0;
+            for (int k = 1; k <= TSAT_MAX_WIDTH; ++k) {
+                st.plane_base[k] = base;
+                base += st.width_count[k];
+            }
+            st.plane_clauses = base;
+            std::vector<uint32_t> npos(V, 0), nneg(V, 0);
+            for (int k = 1; k <= st.K; ++k)
+                for (const uint32_t c : st.buckets[k]) ++((c & 1u) ? nneg : npos)[c >> 1];
+            std::vector<uint32_t> curp(V), curn(V);
+            if (!pure) {
+                st.cid_off.assign((size_t)V + 1, 0);
+                st.cid_mid.assign((size_t)V, 0);
+            }
+            uint64_t total = 0;
+            for (int32_t v = 0; v < V; ++v) {
+                curp[v] = (uint32_t)total;
+                curn[v] = (uint32_t)(total + npos[v]);
+                if (!pure) {
+                    st.cid_off[v] = curp[v];
+                    st.cid_mid[v] = curn[v];
+                }
+                st.max_sign_rec = std::max<uint64_t>(st.max_sign_rec, std::max(npos[v], nneg[v]));
+                total += (uint64_t)npos[v] + nneg[v];
+            }
+            if (!pure) st.cid_off[V] = (uint32_t)total;
+            st.occ_cid.assign(total, 0);
+            for (int k = 1; k <= st.K; ++k) {
+                const auto& b = st.buckets[k];
+                const size_t Cb = b.size() / (size_t)k;
+                for (size_t c = 0; c < Cb; ++c)
+                    for (int e = 0; e < k; ++e) {
+                        const uint32_t code = b[c * k + e];
+                        uint32_t& pos = (code & 1u) ? curn[code >> 1] : curp[code >> 1];
+                        st.occ_cid[pos++] = (uint32_t)(st.plane_base[k] + (int64_t)c);
+                    }
+            }
+        } catch (const std::bad_alloc&) {
+            return fail(TSAT_E_OOM, "host allocation failed while building the clause-index records");
+        }
     }
     return TSAT_OK;
 }

@@ -15,6 +15,10 @@ namespace tsat_host {
 
 constexpr uint32_t kHeavyWords = 768;
 constexpr uint32_t kChunkWords = 512;
+// widest clause of a store whose update gathers the forward's planes of R
+// (R of a clause in binary: 2 planes up to width 3, 4 up to width 15)
+constexpr int32_t kMaxPlaneWidth = 15;
+inline int32_t planes_for_width(int32_t K) { return K <= 3 ? 2 : 4; }
 
 
 // Size limits of the occurrence store.  The record offsets are 32-bit, and
@@ -52,8 +56,17 @@ struct Store {
     int32_t pure_k = 0;
     std::vector<uint32_t> occ_off, occ_mid, occ_data;
     uint64_t max_sign_deg = 0; // most records of one variable and sign
-    // uniform widths 2 and 3: the same records as clause indices within the bucket
-    std::vector<uint32_t> occ_cid;
+    // Clause-index records (every store with 1 <= K <= kMaxPlaneWidth and
+    // fewer than 2^32 clauses and occurrences): per variable, the global
+    // indices of the clauses it occurs in, positive occurrences first; a
+    // clause of width k at position c of its bucket has global index
+    // plane_base[k] + c.  The record offsets are cid_off / cid_mid, or, in a
+    // uniform-width store (whose occurrence records are counted in records
+    // too), occ_off / occ_mid (cid_off stays empty).
+    std::vector<uint32_t> occ_cid, cid_off, cid_mid;
+    std::vector<int64_t> plane_base;   // [TSAT_MAX_WIDTH + 1]; empty without records
+    int64_t plane_clauses = 0;         // clauses of widths >= 1 (rows of the plane array)
+    uint64_t max_sign_rec = 0;         // most clause-index records of one variable and sign
     // generic records: variables with more than kHeavyWords occurrence words,
     // cut at record boundaries into chunks of at most kChunkWords words
     std::vector<uint32_t> heavy, hv_var, hv_chunk, ch_var, ch_beg, ch_end;

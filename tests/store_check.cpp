@@ -176,12 +176,6 @@ static void check_store(const std::vector<Inst>& insts, const Store& st, bool ex
                 if (pure) {
                     const size_t w = (size_t)q * (size_t)(st.pure_k - 1);
                     rest.assign(st.occ_data.begin() + (ptrdiff_t)w, st.occ_data.begin() + (ptrdiff_t)(w + st.pure_k - 1));
-                    if (!st.occ_cid.empty()) {
-                        // the clause index names a clause of the bucket holding lit
-                        const uint32_t cid = st.occ_cid[q];
-                        const uint32_t* cl = &st.buckets[st.pure_k][(size_t)cid * st.pure_k];
-                        CHECK(std::count(cl, cl + st.pure_k, lit) == 1);
-                    }
                     q += 1;
                 } else {
                     const uint32_t k1 = st.occ_data[q];
@@ -194,6 +188,39 @@ static void check_store(const std::vector<Inst>& insts, const Store& st, bool ex
         }
     }
     CHECK(occ_got == occ_want);
+    // clause-index records: per variable and sign, exactly the global
+    // indices of the clauses holding the literal
+    if (st.K >= 1 && st.K <= kMaxPlaneWidth) {
+        CHECK(!st.plane_base.empty());
+        std::map<uint32_t, std::multiset<int64_t>> cid_want, cid_got;
+        int64_t base = 0;
+        for (int k = 1; k <= TSAT_MAX_WIDTH; ++k) {
+            CHECK(st.plane_base[k] == base);
+            if (k <= st.K) {
+                const size_t Cb = st.buckets[k].size() / (size_t)k;
+                for (size_t c = 0; c < Cb; ++c)
+                    for (int e = 0; e < k; ++e) cid_want[st.buckets[k][c * k + e]].insert(base + (int64_t)c);
+            }
+            base += st.width_count[k];
+        }
+        CHECK(st.plane_clauses == base);
+        const std::vector<uint32_t>& off = pure ? st.occ_off : st.cid_off;
+        const std::vector<uint32_t>& mid = pure ? st.occ_mid : st.cid_mid;
+        CHECK(off.size() == (size_t)st.V + 1 && off[st.V] == st.occ_cid.size());
+        uint64_t most = 0;
+        for (int32_t v = 0; v < st.V; ++v) {
+            CHECK(off[v] <= mid[v] && mid[v] <= off[v + 1]);
+            most = std::max<uint64_t>(most, std::max(mid[v] - off[v], off[v + 1] - mid[v]));
+            for (uint32_t q = off[v]; q < off[v + 1]; ++q) {
+                CHECK((int64_t)st.occ_cid[q] < st.plane_clauses);
+                cid_got[2u * (uint32_t)v + (q >= mid[v] ? 1u : 0u)].insert(st.occ_cid[q]);
+            }
+        }
+        CHECK(most == st.max_sign_rec);
+        CHECK(cid_got == cid_want);
+    } else {
+        CHECK(st.occ_cid.empty());
+    }
     // heavy chunks of generic stores tile each heavy variable's records
     if (!pure && !st.hv_var.empty()) {
         for (size_t h = 0; h < st.hv_var.size(); ++h) {
@@ -272,7 +299,7 @@ static void test_limits()
     lim.max_pure_bytes = (uint64_t)st.L * 2 * 4 - 1; // one byte short of the header-less records
     Store g;
     CHECK(build_store(1, nv.data(), off.data(), lits.data(), g, true, lim) == TSAT_OK);
-    CHECK(g.pure_k == 0 && g.occ_cid.empty());
+    CHECK(g.pure_k == 0 && g.occ_cid.size() == (size_t)g.L && g.cid_off.size() == (size_t)g.V + 1);
     CHECK(g.occ_data.size() == (size_t)g.L * 3);
     check_store({in}, g, true);
     lim.max_pure_bytes = (uint64_t)st.L * 2 * 4; // exactly fits

@@ -10,7 +10,7 @@ import oracle as orc
 from paper_2511_07737_amd import gen, tsat
 
 from parity_util import (TOL_ADAM, TOL_GRAD, abs_adjoint, adam_bounds, adam_reference, grad_bound,
-                         make_state, solver_or_skip, sub_cnf)
+                         make_state, one_step_parity, oparams, solver_or_skip, sub_cnf)
 
 pytestmark = pytest.mark.gpu
 
@@ -20,62 +20,6 @@ def solver():
     s = solver_or_skip()
     yield s
     s.close()
-
-
-def oparams(p):
-    return orc.default_params(tau=p.tau, lr0=p.lr0, decay=p.lr_decay, lr_min=p.lr_min, beta1=p.beta1,
-                              beta2=p.beta2, eps=p.eps, weight_decay=p.weight_decay, every=p.decay_every,
-                              restart=p.restart_every, mode=p.norm_mode)
-
-
-def one_step_parity(solver, cnf, N, seed, t, p=None, state=None, check_bits_rows=True):
-    """Full element-by-element parity of one iteration."""
-    p = p or tsat.default_params()
-    print(f"[parity] V={cnf.num_vars} C={cnf.num_clauses} N={N} seed={seed} t={t} tau={p.tau} mode={p.norm_mode}",
-          flush=True)
-    solver.load(cnf)
-    th, m, v = state if state is not None else make_state(cnf.num_vars, N, seed)
-    solver.init_batch(N, init_logits=th)
-    solver.set_state(th, m, v, t)
-    oc = orc.Cnf.from_gen(cnf)
-    # forward: bits (of the call's normalization mode), histogram, loss
-    hist, S, loss = solver.eval(p)
-    b_ref, mu = orc.binarize(th.astype(np.float64), p.norm_mode)
-    b_gpu = tsat.unpack_bits(solver.get_bits(), N)
-    assert np.array_equal(b_gpu, b_ref)
-    H_ref = orc.histogram(oc, b_ref)
-    assert hist.shape == H_ref.shape and np.array_equal(hist.astype(np.int64), H_ref)
-    S_ref, table, loss_ref = orc.smoothmin(H_ref, p.tau)
-    assert np.allclose(S, S_ref, rtol=1e-12, atol=1e-12)
-    assert abs(loss - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-12
-    sat, ok = solver.check()
-    sat_ref, ok_ref = orc.check(oc, b_ref)
-    assert np.array_equal(sat, sat_ref) and np.array_equal(ok, ok_ref)
-    # backward
-    U_gpu, g_gpu = solver.get_grad(p)
-    U_ref = orc.adjoint(oc, b_ref, table)
-    aU = abs_adjoint(oc, b_ref, table)
-    assert (np.abs(U_gpu - U_ref) <= TOL_GRAD * aU + 1e-30).all(), np.abs(U_gpu - U_ref).max()
-    g_ref = orc.norm_backward(th.astype(np.float64), U_ref, p.norm_mode)
-    ag = grad_bound(aU, th, mu, g_ref) if p.norm_mode == orc.MODE_MEAN else aU + np.abs(g_ref)
-    assert (np.abs(g_gpu - g_ref) <= TOL_GRAD * ag + 1e-30).all(), np.abs(g_gpu - g_ref).max()
-    # update (stage 2: the oracle optimizer applied to the GPU's gradient)
-    rep = solver.step(1, params=p)
-    assert rep.steps_done == 1 and rep.next_step == t + 1
-    assert abs(rep.loss - loss_ref) <= 1e-5 * abs(loss_ref) + 1e-12
-    th2, m2, v2, t2 = solver.get_state()
-    assert t2 == t + 1
-    th_r, m_r, v_r, lr = adam_reference(th, m, v, g_gpu, t, p)
-    bt, bm, bv = adam_bounds(th, m, v, g_gpu, t, p, lr, v_r)
-    assert (np.abs(m2 - m_r) <= TOL_ADAM * bm + 1e-30).all()
-    assert (np.abs(v2 - v_r) <= TOL_ADAM * bv + 1e-30).all()
-    assert (np.abs(th2 - th_r) <= TOL_ADAM * bt + 1e-30).all(), np.abs(th2 - th_r).max()
-    # re-binarization of the GPU's own new logits (exact)
-    b2_ref, mu2 = orc.binarize(th2.astype(np.float64), p.norm_mode)
-    if check_bits_rows:
-        b2_gpu = tsat.unpack_bits(solver.get_bits(), N)
-        assert np.array_equal(b2_gpu, b2_ref)
-    return dict(U=U_gpu, g=g_gpu, table=table, H=H_ref)
 
 
 def test_tiny_first_step(solver):

@@ -46,11 +46,21 @@ def test_results_do_not_depend_on_launch_shape(which):
         cnf = mixed_cnf()
     else:
         cnf = [gen.planted_ksat(400 + 100 * j, 4 * (400 + 100 * j), 3, seed=30 + j) for j in range(5)]
-    ref = run(cnf, SHAPES[0])
-    for shape in SHAPES[1:]:
+    # a mixed-width store has two gathers that round differently: the clause
+    # planes by windows, and the other literals' rows (planes off, or the
+    # window gather off); shapes within each give identical results
+    def gather(shape):
+        if which != "mixed":
+            return 0
+        return int(shape.get("clause_planes", 1) == 1 and shape.get("window_gather", 1) == 1)
+
+    refs = {}
+    for shape in SHAPES:
         got = run(cnf, shape)
+        ref = refs.setdefault(gather(shape), got)
         for a, b in zip(ref, got):
             assert np.array_equal(np.asarray(a), np.asarray(b))
+    assert len(refs) == (2 if which == "mixed" else 1)
 
 
 @pytest.mark.parametrize("pure", [True, False])
@@ -66,11 +76,11 @@ def test_autotune_picks_a_candidate_and_keeps_solving(pure):
     # the record group only matters (and is only tuned) for uniform-width stores
     assert c.pure_group in ((1, 2, 4) if pure else (before.pure_group,))
     assert c.fwd_ms > 0 and c.var_ms > 0
-    assert c.clause_planes in ((0, 1) if pure else (before.clause_planes,))
-    # forward targets, then blocks per CU with the clause planes on (by
-    # windows and by records) and, off, with the three record groups (uniform
-    # widths only)
-    assert used == 2 * (5 + (5 * 2 + 5 * 3 if pure else 5))
+    assert c.clause_planes in (0, 1)
+    # forward targets, then blocks per CU with the clause planes on (uniform
+    # widths 2 and 3: by windows and by records; mixed: by windows) and, off,
+    # with the three record groups (uniform widths only)
+    assert used == 2 * (5 + (5 * 2 + 5 * 3 if pure else 5 + 5))
     got = s.launch_config()
     assert (got.fwd_target_blocks, got.var_blocks_per_cu, got.pure_group) == \
         (c.fwd_target_blocks, c.var_blocks_per_cu, c.pure_group)
