@@ -11,7 +11,13 @@ resident in HBM before the timed region.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 10]
                        [--workload large|structured|tiny] [--no-cpu-baseline]
-                       [--no-learned] [--no-autotune] [--calib-copy-mib M]
+                       [--no-learned] [--no-ragged] [--no-stream] [--no-autotune]
+                       [--calib-copy-mib M]
+
+Besides the timed workload the line carries the bandwidth reference kernels,
+the tiny-configuration steps-to-SAT distribution, the learned-versus-random
+start comparison, the ragged 1000-instance configuration and the FP64 oracle
+timed on the host (one thread and all threads).
 """
 from __future__ import annotations
 
@@ -46,40 +52,61 @@ def make_cnf(w):
 
 
 def uses_clause_planes(cnf, N, planes_on):
-    """The update gathers the forward's planes of R (uniform width 2 or 3, N <= 256)."""
+    """The update gathers the forward's planes of R: every clause at most 15
+    wide and at most 256 candidates."""
     import numpy as np
 
-    w = np.unique(cnf.widths())
-    return bool(planes_on) and w.size == 1 and int(w[0]) in (2, 3) and N <= 256
+    w = cnf.widths()
+    return bool(planes_on) and w.size > 0 and int(w.max()) <= 15 and N <= 256
 
 
-def algorithmic_bytes_step_kernel(cnf, N, planes):
-    """Bytes the update step must move once per iteration: theta, m, v read
-    and written (24 B per (variable, candidate)), the next literal rows
-    written (2 rows of N/8 B per variable), the row means (16 B per
-    variable), the record offsets (8 B per variable) and either
-    - with clause planes: the own row (N/8 B per variable), the two planes of
-      every clause (2 x N/8 B per clause) and one clause index per literal
-      (4 B), or
-    - with row gathers: the own rows (2 x N/8 B per variable) and the
-      occurrence store (4 B per word: sum over clauses of k^2 words)."""
+def survey_bytes(cnf, N):
+    """Algorithmic bytes of the path's byte model (per iteration):
+    - update: clause indices (4 B per literal), the current value rows
+      (V N / 8), theta, m, v read and written (24 B per (variable,
+      candidate)) and the next value rows (V N / 8);
+    - fwd: clause codes (4 B per literal) and every value row once (V N / 8);
+    - fwdbwd: the forward and the adjoint as separate passes, codes read
+      twice, rows read twice, the FP32 gradient written once: 8 L + V N / 4 + 4 V N;
+    - step_fused_min: fwd + update (the fused design never moves U);
+    - step_unfused: fwdbwd plus an update that reads U: + 28.125 V N."""
+    V, L = cnf.num_vars, cnf.num_lits
+    VN = V * N
+    upd = 4 * L + VN / 8 + 24 * VN + VN / 8
+    fwd = 4 * L + VN / 8
+    fwdbwd = 8 * L + VN / 4 + 4 * VN
+    return dict(update=upd, fwd=fwd, fwdbwd=fwdbwd, step_fused_min=fwd + upd, step_unfused=fwdbwd + 28.125 * VN)
+
+
+def implementation_bytes(cnf, N, planes):
+    """What the kernels of this implementation move at least once per
+    iteration beyond the byte model (reported separately): with clause
+    planes, the forward writes and the update reads R of every clause in
+    binary (P planes of J words, P = 2 up to width 3, else 4, J = row words);
+    row means (16 B per variable) and record offsets (8 B per variable); the
+    update writes both literal rows (the complement too)."""
     import numpy as np
 
     V, C = cnf.num_vars, cnf.num_clauses
     W = (N + 63) // 64
-    common = 24 * V * N + 2 * V * W * 8 + 16 * V + 8 * V
+    J = W if W <= 2 else (4 if W <= 4 else 8 * ((W + 7) // 8))
+    out = dict(means_offsets=24 * V, complement_rows=V * W * 8)
     if planes:
-        return common + V * W * 8 + 2 * C * W * 8 + 4 * cnf.num_lits
-    occ_words = int((cnf.widths().astype(np.int64) ** 2).sum())
-    return common + 2 * V * W * 8 + 4 * occ_words
+        P = 2 if int(cnf.widths().max()) <= 3 else 4
+        out["planes_write"] = out["planes_read"] = int(C * P * J * 8)
+    else:
+        occ_words = int((cnf.widths().astype(np.int64) ** 2).sum())
+        out["occurrence_records"] = 4 * occ_words
+    return out
 
 
-def algorithmic_bytes_fwd(cnf, N, planes):
-    """Forward histogram: clause codes (4 B per literal), every value row once
-    (V rows of N/8 B; the complements are derived) and, with clause planes,
-    the two planes of every clause written (2 x N/8 B per clause)."""
-    W = (N + 63) // 64
-    return 4 * cnf.num_lits + cnf.num_vars * W * 8 + (2 * cnf.num_clauses * W * 8 if planes else 0)
+def frac_entry(nbytes, ms, kernel=None):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    e = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": int(nbytes), "ms": round(ms, 5)}
+    if kernel:
+        e["kernel"] = kernel
+    return e
 
 
 KERNEL_SOURCES = ["paper_2511_07737_amd/csrc/tsat_kernels.hip", "paper_2511_07737_amd/csrc/tsat_device.h"]
@@ -110,25 +137,51 @@ def measured_traffic(workload):
 
 
 def learned_vs_random():
-    """Steps / time to all-SAT (and to the 99% hand-off) from the trained
-    proposal network's start, from the majority-vote start (Laplace-smoothed
-    positive-occurrence fraction) and from the N(0,1) start, on a held-out planted
-    3-SAT instance V = 100,000, C = 410,000, 128 restarts, same seeds; and
-    steps to all-SAT per instance on 400 small held-out instances solved as
-    one batch."""
+    """The learned proposal's start against the majority-vote start
+    (Laplace-smoothed positive-occurrence fraction) and the N(0,1) start:
+    on 20 held-out planted 3-SAT instances V = 100,000, C = 410,000 (seeds
+    20000..20019), 128 restarts, one batch per arm (steps to the 99%
+    hand-off, lowest unsatisfied count vs step, censored steps and time to
+    all-SAT); and steps to all-SAT per instance on 400 small held-out
+    instances, where the search reaches all-SAT."""
     from paper_2511_07737_amd import learned
 
     if not os.path.exists(learned.DEFAULT_WEIGHTS):
         return None
     print("[bench] learned vs random start", file=sys.stderr, flush=True)
     weights, meta = learned.load_weights()
-    res = learned.compare(weights, V=100_000, restarts=128, max_steps=3600, seeds=(1, 2, 3))
-    res.pop("runs", None)
-    # steps to all-SAT need instances the search solves: a batch of small
-    # held-out instances, per-instance first satisfying iteration
+    res = learned.evaluate_heldout(weights, count=20, V=100_000, restarts=128, max_steps=3600)
+    print("[bench] learned vs random start: small-instance batch", file=sys.stderr, flush=True)
     res["small_batch"] = learned.compare_batch(weights, count=400, vmin=200, vmax=1000, ratio=4.0)
     res["training"] = {k: meta.get(k) for k in ("instances", "rows", "val_accuracy", "final_loss", "epochs")}
     return res
+
+
+def ragged_block(count, max_steps):
+    """The ragged many-instance configuration: `count` planted 3-SAT
+    instances (V log-uniform in [1e3, 2e5], ratio uniform in [3.8, 4.2],
+    seeds 3000 + j), 32 restarts each, one batch replayed from a captured
+    graph with autotuned launch shapes; hand-off phase (stop mode 2), then
+    from the same start to all-SAT or the step cap (censored percentiles)."""
+    from paper_2511_07737_amd import ragged, tsat
+
+    print(f"[bench] ragged: generating {count} instances", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    cnfs = ragged.generate(count, workers=min(16, os.cpu_count() or 1))
+    t_gen = time.perf_counter() - t0
+    params = tsat.default_params(norm_mode=tsat.MODE_NONE, tau=2.0)
+    out = ragged.solve_batch(cnfs, 32, max_steps, params, autotune_iters=2, graph=True)
+    L = out["total_lits"]
+    out["gen_s"] = round(t_gen, 1)
+    out["workload"] = (f"{count} planted 3-SAT instances, V log-uniform in [1000, 200000], ratio uniform in "
+                       f"[3.8, 4.2], 32 restarts each, none-mode tau=2, cap {max_steps} steps")
+    # throughput of the batch iteration (hand-off phase, every instance live)
+    ms = out["handoff"]["ms_per_step"]
+    out["evals_per_s"] = L * 32 / (ms * 1e-3)
+    V = out["total_vars"]
+    step_min = 4 * L + V * 32 / 8 + 4 * L + V * 32 / 8 + 24 * V * 32 + V * 32 / 8
+    out["step_frac_fused_min"] = round(step_min / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def tiny_distribution():
@@ -165,23 +218,95 @@ def tiny_distribution():
     return out
 
 
-def cpu_baseline(cnf, w, n_sample):
-    """The FP64 oracle step, single-threaded, on the same instance with
-    n_sample of the candidates."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_step_threaded(oc, th, m, v, t, threads):
+    """One oracle iteration (Eq. 5 + Eq. 2, R histogram, SmoothMin, adjoint,
+    Eq. 5 backward, AdamW) with each stage's oracle routine run on
+    `threads` parts at once: variables for the row-wise stages, candidates
+    for the histogram and the adjoint (each part on a copy of its columns)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle as orc
+
+    V, N = th.shape
+    p = orc.default_params()
+    rows = np.array_split(np.arange(V), threads)
+    cols = np.array_split(np.arange(N), threads)
+    b = np.empty((V, N), dtype=np.uint8)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        def binarize(r):
+            if r.size:
+                b[r[0]:r[-1] + 1], _ = orc.binarize(th[r[0]:r[-1] + 1], p.mode)
+        list(ex.map(binarize, rows))
+        H = np.zeros((N, oc.K + 1), dtype=np.int64)
+
+        def hist(c):
+            if c.size:
+                H[c[0]:c[-1] + 1] = orc.histogram(oc, np.ascontiguousarray(b[:, c[0]:c[-1] + 1]))
+        list(ex.map(hist, cols))
+        _, table, _ = orc.smoothmin(H, p.tau)
+        U = np.empty((V, N))
+
+        def adj(c):
+            if c.size:
+                U[:, c[0]:c[-1] + 1] = orc.adjoint(oc, np.ascontiguousarray(b[:, c[0]:c[-1] + 1]),
+                                                   np.ascontiguousarray(table[c[0]:c[-1] + 1]))
+        list(ex.map(adj, cols))
+        g = np.empty((V, N))
+
+        def nb(r):
+            if r.size:
+                g[r[0]:r[-1] + 1] = orc.norm_backward(th[r[0]:r[-1] + 1], U[r[0]:r[-1] + 1], p.mode)
+        list(ex.map(nb, rows))
+        lr = orc.lr(t, p)
+
+        def adam(r):
+            if r.size:
+                sl = slice(r[0], r[-1] + 1)
+                orc.adamw(th[sl], m[sl], v[sl], g[sl], lr, t + 1)
+        list(ex.map(adam, rows))
+
+
+def cpu_baseline(cnf, w, n_sample, threads, steps_all):
+    """The FP64 oracle on the host: one single-threaded iteration on
+    n_sample of the candidates (orc.step), and `steps_all` iterations over
+    all candidates with every stage split over `threads` threads."""
     import numpy as np
 
     import oracle as orc
     from paper_2511_07737_amd import gen
 
     oc = orc.Cnf.from_gen(cnf)
+    N = w["N"]
     th = gen.normal_logits(cnf.num_vars, n_sample, w["init_seed"]).astype(np.float64)
     t0 = time.perf_counter()
     orc.step(oc, th, np.zeros_like(th), np.zeros_like(th), 0)
+    dt1 = time.perf_counter() - t0
+    single = dict(value=cnf.num_lits * n_sample / dt1, cores=1, seconds=round(dt1, 2),
+                  sample=f"one oracle iteration (orc.step) with {n_sample} of the {N} candidates")
+    th = gen.normal_logits(cnf.num_vars, N, w["init_seed"]).astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    t0 = time.perf_counter()
+    for t in range(steps_all):
+        oracle_step_threaded(oc, th, m, v, t, threads)
     dt = time.perf_counter() - t0
-    return dict(value=cnf.num_lits * n_sample / dt, unit="clause-literal evals/s", cores=1, kind="oracle",
-                sample=f"one full oracle step (binarize, R, SmoothMin, adjoint, Eq. 5 backward, AdamW) over the "
-                       f"whole instance with {n_sample} of the {w['N']} candidates; {dt:.1f} s single-threaded C FP64",
-                seconds=dt)
+    return dict(value=cnf.num_lits * N * steps_all / dt, unit="clause-literal evals/s", cores=threads, kind="oracle",
+                sample=f"{steps_all} oracle iterations over the whole instance and all {N} candidates, every stage "
+                       f"(binarize, R histogram, SmoothMin, adjoint, Eq. 5 backward, AdamW) split over {threads} "
+                       f"threads; {dt:.1f} s C FP64",
+                cpu_model=cpu_model(), single_thread=single, seconds=dt)
 
 
 def main():
@@ -191,11 +316,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=128, help="candidates of the single-threaded oracle iteration")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="all-candidate oracle iterations on all host threads")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the solve-quality reports: the learned-versus-random start comparison and the "
                          "tiny-configuration steps-to-SAT distribution")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged many-instance configuration")
+    ap.add_argument("--ragged-count", type=int, default=1000)
+    ap.add_argument("--ragged-steps", type=int, default=3600)
+    ap.add_argument("--no-stream", action="store_true", help="skip the bandwidth reference kernels")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, launch one plain device copy kernel of this many MiB (read + write), "
                          "the reference point for scaling hardware byte counters")
@@ -236,18 +366,16 @@ def main():
     value = evals_per_step * args.steps / sec
 
     planes = uses_clause_planes(cnf, N, s.launch_config().clause_planes)
-    step_bytes = algorithmic_bytes_step_kernel(cnf, N, planes)
-    fwd_bytes = algorithmic_bytes_fwd(cnf, N, planes)
+    sb = survey_bytes(cnf, N)
+    impl = implementation_bytes(cnf, N, planes)
     names = ["fwd_hist", "smin_tables", "var_step"]
     dom = int(np.argmax(kms))
-    dom_bytes = {0: fwd_bytes, 2: step_bytes}.get(dom)
     roofline = None
-    if dom_bytes is not None:
-        achieved = dom_bytes / (kms[dom] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
-                    "kernel": names[dom],
-                    "bytes_per_launch": dom_bytes}
+    if dom in (0, 2):
+        roofline = frac_entry(sb["update"] if dom == 2 else sb["fwd"], kms[dom], names[dom])
+        roofline["traffic"] = measured_traffic(args.workload) if dom == 2 else None
+        roofline["impl_bytes_per_launch"] = {k: v for k, v in impl.items()
+                                             if dom == 2 or k == "planes_write"}
     out = {
         "metric": "clause-literal evals/s (fwd+bwd, % HBM peak); steps-to-all-SAT learned vs random",
         "value": value,
@@ -265,27 +393,52 @@ def main():
                    "steps_per_launch_sequence": args.steps, "launch": s.launch_config().as_dict(),
                    "autotuned": tuned is not None},
         "roofline": roofline,
+        # the forward (and exact clause check) against its own byte model
+        "roofline_fwd": frac_entry(sb["fwd"], kms[0], "fwd_hist"),
+        # the whole iteration against the fused minimum (forward + update:
+        # U never reaches memory) and against the unfused byte model
+        "roofline_step": {"ms_per_step": round(ms_per_step, 5),
+                          "bytes_fused_min": int(sb["step_fused_min"]),
+                          "frac_fused_min": round(sb["step_fused_min"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "bytes_unfused": int(sb["step_unfused"]),
+                          "frac_unfused": round(sb["step_unfused"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        # the metric's fwd+bwd byte model over the smallest timed region that
+        # holds forward and backward (the whole iteration: the backward is
+        # fused with the update)
+        "roofline_fwdbwd": {"bytes": int(sb["fwdbwd"]), "ms": round(ms_per_step, 5),
+                            "frac": round(sb["fwdbwd"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "evals_per_s": value},
         "kernels_ms": {n: round(x, 5) for n, x in zip(names, kms)},
         "kernel_iters": kiters,
-        "fwd_gbs": round(fwd_bytes / (kms[0] * 1e-3) / 1e9, 1),
-        "step_kernel_gbs": round(step_bytes / (kms[2] * 1e-3) / 1e9, 1),
         "best_sat_count": rep.best_sat_count,
         "first_sat_step": rep.first_sat_step,
         # the exact clause check is the forward histogram: bin 0 counts the
         # unsatisfied clauses of every candidate
         "check_pairs_per_s": cnf.num_clauses * N / (kms[0] * 1e-3),
     }
-    if not args.no_learned:
-        out["tiny"] = tiny_distribution()
-    if not args.no_learned:
-        out["learned_vs_random"] = learned_vs_random()
+    if not args.no_stream:
+        # bandwidth references on 1 GiB arrays: the practical ceilings the
+        # fractions above can be read against
+        nb = 1 << 30
+        ref = {}
+        for kind, name, moved in ((0, "copy_x4", 2), (1, "rw3_x4", 6), (2, "rw3_rows", 6)):
+            ms = s.stream_calibrate(nb, kind, reps=5)
+            ref[name] = {"gbs": round(moved * nb / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+        out["stream_ceiling"] = ref
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib << 20
         ms = s.copy_calibrate(nb)  # one copy kernel: nb bytes read, nb bytes written
         out["calib_copy"] = {"bytes": nb, "ms": ms, "gbs": round(2 * nb / (ms * 1e-3) / 1e9, 1)}
+    s.close()
+    if not args.no_learned:
+        out["tiny"] = tiny_distribution()
+        out["learned_vs_random"] = learned_vs_random()
+    if not args.no_ragged:
+        out["ragged"] = ragged_block(args.ragged_count, args.ragged_steps)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cb = cpu_baseline(cnf, w, min(args.cpu_sample, N))
+        threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
+        print(f"[bench] cpu baseline (oracle, 1 and {threads} threads)", file=sys.stderr, flush=True)
+        cb = cpu_baseline(cnf, w, min(args.cpu_sample, N), threads, args.cpu_steps)
         out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
         out["gpu_over_cpu"] = value / cb["value"]
     else:

@@ -566,6 +566,38 @@ int32_t tsat_get_timing(tsat_solver* s, double* ms, int32_t* iters);
  * E_OOM if the buffers cannot be allocated. */
 int32_t tsat_copy_calibrate(tsat_solver* s, int64_t bytes, double* ms);
 
+/* Independent literal rows (Sec. III-B writes the real-valued assignment
+ * as 2V x N, one row per literal; the incomplete-assignment passage of
+ * Sec. III-A): with enable = 1 the next tsat_init_batch holds 2V logit
+ * rows, row 2v for x_v and row 2v + 1 for not-x_v, each normalized (Eq. 5)
+ * and binarized (Eq. 2) on its own, so a candidate may set both literals of
+ * a variable (either satisfies its clauses: a "don't care") or neither.
+ * R counts a clause's literals whose own row is 1; the adjoint of a
+ * literal row is the sum of dL/dR over the clauses holding that literal
+ * (+1 through the straight-through estimator), followed by the Eq. 5
+ * backward and AdamW of that row.  Every host array of the batch is then
+ * [2V][N] (init_logits, logits, state, U and g) and tsat_get_bits returns
+ * all 2V literal rows ([2V][ceil(N/64)]).  Single-instance solvers with
+ * clauses at most 15 wide, N <= 256, and the clause planes and window gather
+ * on (E_ARG otherwise, at this call or at tsat_init_batch); the proposal
+ * start, the hand-off buffer, tsat_get_assignment and witnesses need
+ * complete assignments (E_STATE).  Calling it drops the current batch;
+ * enable = 0 returns to one row per variable.  E_STATE before a CNF is
+ * loaded. */
+int32_t tsat_set_literal_rows(tsat_solver* s, int32_t enable);
+
+/* Bandwidth references for the roofline: allocates arrays of `bytes` each
+ * (a positive multiple of 16384), runs one untimed and then `reps` (1..1000)
+ * timed launches of a streaming kernel over them and returns the average
+ * device time per launch in *ms (may be NULL).  kind 0: copy of one array
+ * into another (bytes read + bytes written), 16-byte non-temporal accesses,
+ * four loads in flight per thread; kind 1: three arrays read and written in
+ * place (3 bytes read + 3 bytes written), same accesses; kind 2: as kind 1
+ * with the update kernels' pattern (rows of 256 floats, one 4-byte load per
+ * lane and array element).  E_ARG for sizes or kinds out of range, E_OOM if
+ * the arrays cannot be allocated; the arrays are freed before returning. */
+int32_t tsat_stream_calibrate(tsat_solver* s, int64_t bytes, int32_t kind, int32_t reps, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,6 +106,9 @@ struct SminArgs {
 
 struct VarArgs {
     int32_t V, N, W, Np, K1, mode;
+    int32_t lit_rows;         // 1: V rows of logits, each one literal's own row of
+                              // bits (independent literal rows); 0: a variable
+                              // row writes its value and complement rows
     int32_t pure_k;           // 2..4: every clause has this width and the records
                               // carry no header; 0: generic records
     int32_t group;            // records per scalar-load group in the pure kernel

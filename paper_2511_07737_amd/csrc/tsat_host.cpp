@@ -57,6 +57,13 @@ struct tsat_solver {
     DBuf heavy, hv_var, hv_chunk, ch_var, ch_beg, ch_end; // chunked heavy variables (generic stores)
     DBuf partial, partial_scr; // FP64 partial sums of the chunks, for the step / for evaluations
 
+    // independent literal rows (one logit row per literal, 2V rows): requested
+    // for the next batch, and the layout of the current one (1 or 2 rows per
+    // variable); lro: each literal's clause-index record range
+    int32_t lit_rows_req = 0;
+    int32_t rows_per_var = 1;
+    DBuf lro;
+
     // batch
     int32_t N = 0, W = 0, Np = 0;
     DBuf lits[2];
@@ -114,6 +121,9 @@ struct tsat_solver {
 };
 
 static int32_t K1_of(const tsat_solver* s) { return s->st.K + 1; }
+
+// logit rows of the batch: one per variable, or one per literal
+static size_t theta_rows(const tsat_solver* s) { return (size_t)s->rows_per_var * s->st.V; }
 
 static int32_t set_dev(tsat_solver* s)
 {
@@ -428,6 +438,20 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     return a;
 }
 
+// The batch's own update launches: with independent literal rows the rows
+// are the 2V literals, each gathering its own clause-index records (all
+// counted as positive occurrences: lro[l] .. lro[l + 1]).
+static void batch_rows(const tsat_solver* s, VarArgs& a)
+{
+    if (s->rows_per_var != 2) return;
+    a.V = 2 * s->st.V;
+    a.lit_rows = 1;
+    a.occ_off = a.cid_off = s->lro.as<uint32_t>();
+    a.occ_mid = a.cid_mid = s->lro.as<uint32_t>() + 1;
+    a.var_inst = nullptr;
+    a.window = 1;
+}
+
 // FP64 partial rows of the heavy-variable chunks for N candidates
 static int32_t ensure_partial(tsat_solver* s, DBuf& buf, int32_t N)
 {
@@ -490,7 +514,8 @@ static int32_t binarize_current(tsat_solver* s, int32_t mode)
     a.mu_next = s->mu[s->cur].as<double>();
     a.theta = s->theta.as<float>();
     a.ctrl = s->ctrl.as<Ctrl>();
-    HIPCHK(launch_var(a, VOP_BINARIZE, var_blocks(s, s->st.V), s->stream));
+    batch_rows(s, a);
+    HIPCHK(launch_var(a, VOP_BINARIZE, var_blocks(s, a.V), s->stream));
     s->bits_mode = mode;
     return TSAT_OK;
 }
@@ -618,6 +643,9 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     for (auto& u : s->wide_units) delete u.second.first;
     s->wide_units.clear();
     s->loaded = false;
+    s->lit_rows_req = 0;
+    s->rows_per_var = 1;
+    s->lro.release();
     s->N = s->W = s->Np = 0;
     s->scr_Np = 0;
     s->prop_valid = false;
@@ -739,7 +767,15 @@ int32_t tsat_load_dimacs(tsat_solver* s, const char* path)
 static int32_t alloc_batch(tsat_solver* s, int32_t N)
 {
     const int32_t W = (N + 63) / 64, Np = 64 * W, K1 = K1_of(s);
-    const size_t VN = (size_t)s->st.V * N;
+    if (s->lit_rows_req) {
+        // independent literal rows run only on the window gather of the
+        // forward's clause planes
+        if (!plane_path(s, N))
+            return fail(TSAT_E_ARG, "independent literal rows need the clause-plane window gather: N <= 256, "
+                                    "clauses at most %d wide, clause planes and the window gather on", kMaxPlaneWidth);
+    }
+    s->rows_per_var = s->lit_rows_req ? 2 : 1;
+    const size_t VN = theta_rows(s) * N;
     const size_t ni = (size_t)s->st.n_inst;
     if ((size_t)K1 * Np * 4 > 64 * 1024)
         return fail(TSAT_E_ARG, "(max_width+1) * 64*ceil(N/64) * 4 bytes = %zu exceeds the 64 KiB table limit",
@@ -751,7 +787,7 @@ static int32_t alloc_batch(tsat_solver* s, int32_t N)
     for (int b = 0; b < 2; ++b) {
         RET(s->lits[b].alloc(lit_words * 8, "literal rows"));
         HIPCHK(launch_fill_u32(s->lits[b].as<uint32_t>(), (int64_t)lit_words * 2, 0u, s->stream));
-        RET(s->mu[b].alloc((size_t)s->st.V * 8, "row means"));
+        RET(s->mu[b].alloc(theta_rows(s) * 8, "row means"));
     }
     RET(s->theta.alloc(VN * 4, "theta"));
     RET(s->m.alloc(VN * 4, "m"));
@@ -784,7 +820,7 @@ int32_t tsat_init_batch(tsat_solver* s, int32_t N, uint64_t seed, const float* i
     HIPCHK(hipStreamSynchronize(s->stream));
     s->N = 0;
     RET(alloc_batch(s, N));
-    const size_t VN = (size_t)s->st.V * N;
+    const size_t VN = theta_rows(s) * N;
     if (init_logits) HIPCHK(hipMemcpyAsync(s->theta.p, init_logits, VN * 4, hipMemcpyHostToDevice, s->stream));
     else HIPCHK(launch_init_normal(s->theta.as<float>(), (int64_t)VN, seed, s->stream));
     RET(binarize_current(s, s->params.norm_mode));
@@ -876,6 +912,7 @@ int32_t tsat_init_from_proposal(tsat_solver* s, int32_t N, uint64_t seed, const 
     RET(need_loaded(s));
     if (N < 1 || N > TSAT_MAX_STEP_N) return fail(TSAT_E_ARG, "N must be in [1, %d] (got %d)", TSAT_MAX_STEP_N, N);
     if (!p_true && !s->prop_valid) return fail(TSAT_E_STATE, "no proposal: pass p_true or call tsat_propose first");
+    if (s->lit_rows_req) return fail(TSAT_E_STATE, "the proposal start draws complete assignments (literal rows are on)");
     HIPCHK(hipStreamSynchronize(s->stream));
     const size_t V = (size_t)s->st.V;
     if (p_true) {
@@ -969,7 +1006,8 @@ int32_t tsat_step(tsat_solver* s, int32_t max_steps, const tsat_params* params, 
     va.ctrl = ctrl;
     va.ictrl = s->ictrl.as<InstCtrl>();
     va.witness = s->witness.as<uint8_t>();
-    const int vblocks = var_blocks(s, s->st.V, var_occupancy(va, VOP_STEP));
+    batch_rows(s, va);
+    const int vblocks = var_blocks(s, va.V, var_occupancy(va, VOP_STEP));
     RET(prepare_units(s, s->N));
 
     const bool graph = s->use_graph && !s->timing;
@@ -1201,6 +1239,12 @@ int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed)
     g_err.clear();
     RET(need_batch(s));
     if (!packed) return fail(TSAT_E_ARG, "packed is NULL");
+    if (s->rows_per_var == 2) { // every literal row
+        HIPCHK(hipMemcpyAsync(packed, s->lits[s->cur].p, (size_t)2 * s->st.V * s->W * 8, hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        return TSAT_OK;
+    }
     // even literal rows hold the variable values: pack them on the device,
     // then one contiguous copy
     const size_t n = (size_t)s->st.V * s->W;
@@ -1214,6 +1258,7 @@ int32_t tsat_get_bits(tsat_solver* s, uint64_t* packed)
 
 static int32_t column_values(tsat_solver* s, int32_t cand, uint32_t v0, uint32_t v1, uint8_t* vals)
 {
+    if (s->rows_per_var == 2) return fail(TSAT_E_STATE, "independent literal rows hold no complete assignment");
     const size_t n = v1 - v0;
     std::vector<uint64_t> col(n);
     if (n) {
@@ -1249,7 +1294,7 @@ int32_t tsat_get_witness_instance(tsat_solver* s, int32_t inst, uint8_t* vals, i
     const uint32_t v0 = s->st.var_base[(size_t)inst], v1 = s->st.var_base[(size_t)inst + 1];
     // a frozen instance still holds the satisfying candidate; otherwise the
     // update of the step that found it recorded it
-    if (x.frozen) return column_values(s, x.sat_cand, v0, v1, vals);
+    if (x.frozen || s->rows_per_var == 2) return column_values(s, x.sat_cand, v0, v1, vals);
     HIPCHK(hipMemcpy(vals, s->witness.as<uint8_t>() + v0, v1 - v0, hipMemcpyDeviceToHost));
     return TSAT_OK;
 }
@@ -1273,7 +1318,7 @@ int32_t tsat_set_logits(tsat_solver* s, const float* theta)
     g_err.clear();
     RET(need_batch(s));
     if (!theta) return fail(TSAT_E_ARG, "theta is NULL");
-    HIPCHK(hipMemcpyAsync(s->theta.p, theta, (size_t)s->st.V * s->N * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->theta.p, theta, theta_rows(s) * s->N * 4, hipMemcpyHostToDevice, s->stream));
     RET(binarize_current(s, s->params.norm_mode));
     HIPCHK(hipStreamSynchronize(s->stream));
     return TSAT_OK;
@@ -1286,7 +1331,7 @@ int32_t tsat_set_state(tsat_solver* s, const float* theta, const float* m, const
     g_err.clear();
     RET(need_batch(s));
     if (!theta || t < 0) return fail(TSAT_E_ARG, "theta is NULL or t < 0");
-    const size_t VN = (size_t)s->st.V * s->N;
+    const size_t VN = theta_rows(s) * s->N;
     HIPCHK(hipMemcpyAsync(s->theta.p, theta, VN * 4, hipMemcpyHostToDevice, s->stream));
     if (m) HIPCHK(hipMemcpyAsync(s->m.p, m, VN * 4, hipMemcpyHostToDevice, s->stream));
     else HIPCHK(launch_fill_u32(s->m.as<uint32_t>(), (int64_t)VN, 0u, s->stream));
@@ -1301,7 +1346,7 @@ int32_t tsat_get_state(tsat_solver* s, float* theta, float* m, float* v, int64_t
 {
     g_err.clear();
     RET(need_batch(s));
-    const size_t VN = (size_t)s->st.V * s->N;
+    const size_t VN = theta_rows(s) * s->N;
     if (theta) HIPCHK(hipMemcpyAsync(theta, s->theta.p, VN * 4, hipMemcpyDeviceToHost, s->stream));
     if (m) HIPCHK(hipMemcpyAsync(m, s->m.p, VN * 4, hipMemcpyDeviceToHost, s->stream));
     if (v) HIPCHK(hipMemcpyAsync(v, s->v.p, VN * 4, hipMemcpyDeviceToHost, s->stream));
@@ -1376,7 +1421,7 @@ int32_t tsat_get_grad(tsat_solver* s, const tsat_params* params, float* U, float
     RET(validate_params(&p));
     RET(ensure_mode(s, p.norm_mode));
     RET(ensure_scratch(s, s->N));
-    const size_t VN = (size_t)s->st.V * s->N;
+    const size_t VN = theta_rows(s) * s->N;
     RET(s->tmp.reserve(VN * 8, "gradient copies"));
     RET(eval_rows(s, p, s->lits[s->cur].as<uint64_t>(), s->N, nullptr, nullptr, nullptr, nullptr, nullptr,
                   s->table_scr.as<float>(), s->stream));
@@ -1388,7 +1433,8 @@ int32_t tsat_get_grad(tsat_solver* s, const tsat_params* params, float* U, float
     va.U_out = s->tmp.as<float>();
     va.g_out = s->tmp.as<float>() + VN;
     va.g_transposed = 0;
-    HIPCHK(launch_var(va, VOP_GRAD, var_blocks(s, s->st.V), s->stream));
+    batch_rows(s, va);
+    HIPCHK(launch_var(va, VOP_GRAD, var_blocks(s, va.V), s->stream));
     if (U) HIPCHK(hipMemcpyAsync(U, va.U_out, VN * 4, hipMemcpyDeviceToHost, s->stream));
     if (g) HIPCHK(hipMemcpyAsync(g, va.g_out, VN * 4, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -1401,6 +1447,7 @@ int32_t tsat_extract_partial(tsat_solver* s, int32_t max_cands, int32_t k, int32
     g_err.clear();
     RET(need_batch(s));
     RET(need_single(s));
+    if (s->rows_per_var == 2) return fail(TSAT_E_STATE, "the hand-off buffer takes complete assignments (literal rows are on)");
     if (max_cands < 1 || max_cands > s->N) return fail(TSAT_E_ARG, "max_cands must be in [1, %d]", s->N);
     if (k <= 0) k = s->params.k_partial;
     if (k <= 0) k = (int32_t)std::max<int64_t>(20, ((int64_t)s->st.V + 9999) / 10000);
@@ -1707,6 +1754,8 @@ int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg)
     g_err.clear();
     if (!s || !cfg) return fail(TSAT_E_ARG, "NULL argument");
     RET(check_launch_config(cfg));
+    if (s->rows_per_var == 2 && s->N > 0 && (!cfg->clause_planes || !cfg->window_gather))
+        return fail(TSAT_E_ARG, "independent literal rows need the clause planes and the window gather");
     RET(set_dev(s));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->drop_graph();
@@ -1774,9 +1823,9 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
     // with clause planes the record group does not apply (the planes come in
     // by 64-record windows or record by record); the forward writes the
     // planes, so the shapes are compared on forward + update time
-    for (int cp = planes_apply ? 1 : 0; cp >= 0; --cp) {
+    for (int cp = planes_apply ? 1 : 0; cp >= (s->rows_per_var == 2 ? 1 : 0); --cp) {
         const int ngroups = (pure && !cp) ? 3 : 1;
-        const int nwin = (cp && uniform_plane_store(s)) ? 2 : 1;
+        const int nwin = (cp && uniform_plane_store(s) && s->rows_per_var == 1) ? 2 : 1;
         for (int pc : kPerCu) {
             for (int gi = 0; gi < ngroups; ++gi) {
                 for (int wi = 0; wi < nwin; ++wi) {
@@ -1852,6 +1901,42 @@ int32_t tsat_copy_calibrate(tsat_solver* s, int64_t bytes, double* ms)
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return fail(TSAT_E_HIP, "copy kernel failed: %s", hipGetErrorString(err));
     if (ms) *ms = t;
+    return TSAT_OK;
+}
+
+int32_t tsat_set_literal_rows(tsat_solver* s, int32_t enable)
+{
+    g_err.clear();
+    RET(need_loaded(s));
+    if (enable != 0 && enable != 1) return fail(TSAT_E_ARG, "enable must be 0 or 1");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (enable) {
+        RET(need_single(s));
+        if (!s->occ_cid.p) return fail(TSAT_E_ARG, "independent literal rows need clauses at most %d wide", kMaxPlaneWidth);
+        if (s->st.max_sign_rec >= 65536) return fail(TSAT_E_ARG, "a literal occurs in 65536 or more clauses");
+        // literal l = 2 v + neg owns the records [lro[l], lro[l + 1]): the
+        // variable's positive records, then its negative ones
+        const std::vector<uint32_t>& off = s->st.cid_off.empty() ? s->st.occ_off : s->st.cid_off;
+        const std::vector<uint32_t>& mid = s->st.cid_off.empty() ? s->st.occ_mid : s->st.cid_mid;
+        const size_t V = (size_t)s->st.V;
+        std::vector<uint32_t> lro;
+        try {
+            lro.resize(2 * V + 1);
+        } catch (const std::bad_alloc&) {
+            return fail(TSAT_E_OOM, "host allocation failed");
+        }
+        for (size_t v = 0; v < V; ++v) {
+            lro[2 * v] = off[v];
+            lro[2 * v + 1] = mid[v];
+        }
+        lro[2 * V] = off[V];
+        RET(s->lro.alloc((2 * V + 1) * 4, "literal record offsets"));
+        HIPCHK(hipMemcpy(s->lro.p, lro.data(), (2 * V + 1) * 4, hipMemcpyHostToDevice));
+    }
+    s->lit_rows_req = enable;
+    // the layout changes with the next batch; the current one is dropped
+    s->drop_graph();
+    s->N = 0;
     return TSAT_OK;
 }
 

@@ -497,8 +497,12 @@ __device__ __forceinline__ void write_bits(const VarArgs& a, uint32_t v, uint32_
         const uint64_t bal = ballot64(p);
         const uint64_t vm = ballot64(valid[j]);
         if (lane == 0) {
-            a.lits_next[(size_t)(2 * v) * W + j] = bal;
-            a.lits_next[(size_t)(2 * v + 1) * W + j] = ~bal & vm;
+            if (a.lit_rows) { // row v is a literal of its own
+                a.lits_next[(size_t)v * W + j] = bal;
+            } else {
+                a.lits_next[(size_t)(2 * v) * W + j] = bal;
+                a.lits_next[(size_t)(2 * v + 1) * W + j] = ~bal & vm;
+            }
         }
     }
 }
@@ -595,7 +599,7 @@ __device__ __forceinline__ void var_tail(const VarArgs& a, const StepScalars& c,
         }
         s2 += (double)th[j];
     }
-    if (witness && lane == 0) a.witness[v] = (uint8_t)((oP[wcand >> 6] >> (wcand & 63)) & 1u);
+    if (witness && lane == 0 && !a.lit_rows) a.witness[v] = (uint8_t)((oP[wcand >> 6] >> (wcand & 63)) & 1u);
     bool pos = true;
     if (a.mode == 1) {
         const double mu2 = wave_sum(s2) * a.inv_n;
@@ -609,7 +613,7 @@ __device__ __forceinline__ void var_tail(const VarArgs& a, const StepScalars& c,
 // row means equal to the current ones so the host's buffer swap stays valid.
 __device__ __forceinline__ void copy_bits_on_stop(const VarArgs& a)
 {
-    const size_t n = (size_t)2 * a.V * a.W;
+    const size_t n = (size_t)(a.lit_rows ? 1 : 2) * a.V * a.W; // rows of literals
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) a.lits_next[e] = a.lits_cur[e];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)a.V; e += stride)
@@ -622,8 +626,9 @@ template <int J>
 __device__ __forceinline__ void keep_variable(const VarArgs& a, uint32_t v, uint32_t lane)
 {
     const int W = a.W;
-    if (lane < (uint32_t)(2 * W)) {
-        const size_t e = (size_t)(2 * v) * W + lane;
+    const int nw = a.lit_rows ? W : 2 * W; // words of the variable's (or literal's) rows
+    if (lane < (uint32_t)nw) {
+        const size_t e = (size_t)(a.lit_rows ? v : 2 * v) * W + lane;
         a.lits_next[e] = a.lits_cur[e];
     }
     if (lane == 0) a.mu_next[v] = a.mu_cur[v];
@@ -720,7 +725,7 @@ __device__ void mix_rows(const VarArgs& a)
             }
             s += (double)x;
         }
-        if (vi.witness && lane == 0) {
+        if (vi.witness && lane == 0 && !a.lit_rows) {
             const uint64_t w = a.lits_cur[(size_t)(2 * v) * W + (vi.wcand >> 6)];
             a.witness[v] = (uint8_t)((w >> (vi.wcand & 63)) & 1u);
         }
@@ -1693,7 +1698,7 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
             load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
             bool clamped = false;
             const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
-            const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+            const uint64_t* ownp = a.lits_cur + (size_t)(a.lit_rows ? v : 2 * v) * W;
             uint64_t oP[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
@@ -1923,27 +1928,53 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
 // block, a batch one per wave (the instance at hand).
 // ---------------------------------------------------------------------------
 
-// [R >= r] for the constant r, bit-sliced: R = sum_p 2^p planes[p].  From the
-// lowest bit up, t = [R restricted to bits < p >= r restricted to bits < p];
-// bit p of r set: t = plane_p & t, clear: t = plane_p | t.
-template <int P, int R>
-__device__ __forceinline__ uint64_t level_ge(const uint64_t (&pl)[P])
+// Thermometer of a bit-sliced R = sum_p 2^p pl[p] (P = 2 or 4 planes):
+// ge[r - 1] = [R >= r] for r = 1 .. KT, built up bit by bit: the levels of
+// the lower q bits give those of q + 1 bits as (new bit) OR (lower levels)
+// below 2^q, the new bit itself at 2^q, and (new bit) AND (lower levels)
+// above.  All are ORs and ANDs of the planes (no constant-true term), so
+// planes masked to a record set give levels masked to that set.
+template <int P, int KT>
+__device__ __forceinline__ void thermometer(const uint64_t (&pl)[P], uint64_t (&ge)[KT])
 {
-    uint64_t t = ~0ull;
+    uint64_t lv[15]; // levels 1 .. 2^q - 1 of the lower q bits
+    lv[0] = pl[0];
+    int n = 1; // 2^q - 1
 #pragma unroll
-    for (int p = 0; p < P; ++p) t = ((R >> p) & 1) ? (pl[p] & t) : (pl[p] | t);
-    if constexpr ((R >> P) != 0) t = 0ull; // r beyond what P bits hold
-    return t;
+    for (int q = 1; q < P; ++q) {
+        const uint64_t b = pl[q];
+        uint64_t nx[15];
+#pragma unroll
+        for (int r = 1; r <= 15; ++r) {
+            if (r > 2 * n + 1) break;
+            if (r <= n) nx[r - 1] = b | lv[r - 1];
+            else if (r == n + 1) nx[r - 1] = b;
+            else nx[r - 1] = b & lv[r - n - 2];
+        }
+        n = 2 * n + 1;
+#pragma unroll
+        for (int r = 0; r < 15; ++r)
+            if (r < n) lv[r] = nx[r];
+    }
+#pragma unroll
+    for (int r = 0; r < KT; ++r) ge[r] = r < n ? lv[r] : 0ull;
 }
 
-template <int P, int KT, int R = 1>
+// Signed level counts of one variable in one window: with the records of
+// its positive occurrences in mp and of its negative ones in mn (disjoint),
+// popc(mn ^ (G & (mp | mn))) = popc(G & mp) + |mn| - popc(G & mn), so one
+// popcount per level gives (positive - negative records with R >= r) + |mn|.
+template <int P, int KT>
 __device__ __forceinline__ void count_levels(const uint64_t (&pl)[P], uint64_t mp, uint64_t mn, uint32_t (&cnt)[KT])
 {
-    if constexpr (R <= KT) {
-        const uint64_t t = level_ge<P, R>(pl);
-        cnt[R - 1] += (uint32_t)__popcll(t & mp) + ((uint32_t)__popcll(t & mn) << 16);
-        count_levels<P, KT, R + 1>(pl, mp, mn, cnt);
-    }
+    const uint64_t m = mp | mn;
+    uint64_t pm[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) pm[p] = pl[p] & m;
+    uint64_t ge[KT];
+    thermometer<P, KT>(pm, ge);
+#pragma unroll
+    for (int r = 0; r < KT; ++r) cnt[r] += (uint32_t)__popcll(mn ^ ge[r]);
 }
 
 // Planes of records [w, w + 64) (records at or past `end` read as zero),
@@ -2025,9 +2056,8 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
                     for (int j = 0; j < J; ++j) my_gt[(r * J + j) * 64 + lane] = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
             }
             const uint32_t r0 = sload(a.cid_off + v), rm = sload(a.cid_mid + v), r1 = sload(a.cid_off + v + 1);
-            // per level r and word j: positive records with R >= r in the low
-            // 16 bits, negative in the high (the host keeps every variable
-            // below 2^16 records per sign on this path)
+            // per level r and word j: (positive - negative records with
+            // R >= r) + (negative records), summed over the windows
             uint32_t cnt[J][KT];
 #pragma unroll
             for (int j = 0; j < J; ++j)
@@ -2056,12 +2086,16 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
             load_row<J, OP, false>(a, v, lane, th, mm, vv, valid);
             bool clamped = false;
             const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
-            const uint64_t* ownp = a.lits_cur + (size_t)(2 * v) * W;
+            const uint64_t* ownp = a.lits_cur + (size_t)(a.lit_rows ? v : 2 * v) * W;
             uint64_t oP[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) oP[j] = sload(ownp + j);
-            // U = sum over r of (positive - negative records with R = r) dL/dR[r]
-            const uint32_t total = (rm - r0) | ((r1 - rm) << 16);
+            // U = sum over r of (positive - negative records with R = r)
+            // dL/dR[r]: with D_r = cnt[r - 1] - dn (positive - negative
+            // records with R >= r), that difference is D_r - D_(r+1), i.e.
+            // dp - cnt[0] at r = 0, cnt[r - 1] - cnt[r] inside and cnt[K - 1] - dn
+            // at the widest clause width K (levels above K count nothing)
+            const int32_t dp = (int32_t)(rm - r0), dn = (int32_t)(r1 - rm);
             double U[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) {
@@ -2069,9 +2103,9 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
 #pragma unroll
                 for (int r = 0; r <= KT; ++r) {
                     if (r >= K1) break; // no clause is wider than the store's widest
-                    const uint32_t e = (r == 0 ? total : cnt[j][r - 1]) - (r < KT ? cnt[j][r] : 0u);
-                    const int32_t d = (int32_t)(e & 0xffffu) - (int32_t)(e >> 16);
-                    u = fmaf((float)d, my_gt[(r * J + j) * 64 + lane], u);
+                    const int32_t hi = r == 0 ? dp + dn : (int32_t)cnt[j][r - 1];
+                    const int32_t lo = (r < KT && r + 1 < K1) ? (int32_t)cnt[j][r] : dn;
+                    u = fmaf((float)(hi - lo - (r == 0 ? dn : 0)), my_gt[(r * J + j) * 64 + lane], u);
                 }
                 U[j] = (double)u;
             }
@@ -2082,6 +2116,143 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
         if (ballot64(bad != 0) && lane == 0) atomicOr(&a.ctrl->nonfinite, 1);
         advance_step(a);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Forward of the wide clauses (widths 5 .. 15) when the clause planes are on:
+// two passes over every wide bucket, one launch each.
+//
+// fwd_planes_kernel: one thread per (clause, candidate dword): R of 32
+// candidates as a bit-sliced binary counter (P = 4 planes: a 1-bit add per
+// literal), written as the clause's planes.
+// planes_hist_kernel: the histogram of R from those planes: a wave takes 64
+// consecutive clauses of a unit, loads their planes (lane r: clause r),
+// transposes every plane word across the wave (lane l: candidate 64 j + l,
+// bit r: clause r) and counts per level r the clauses with R >= r
+// (thermometer of the planes, one popcount per level); H[r] = #(R >= r) -
+// #(R >= r + 1).  The block adds its four waves' counts in LDS, then into
+// the global histogram (integer atomics, so the result is exact).
+// ---------------------------------------------------------------------------
+
+template <int KMAX>
+__global__ __launch_bounds__(256) void fwd_planes_kernel(FwdArgs a)
+{
+    if (a.ctrl && a.ctrl->stop) return;
+    const FwdUnit u = a.units[blockIdx.x];
+    if (a.ictrl && a.ictrl[u.inst].frozen) return;
+    const int k = u.pad;
+    const uint32_t* codes = a.wide_codes[k];
+    const int64_t base = a.wide_base[k];
+    const int Dn = a.Dn, S = 256 / Dn;
+    const int slot = threadIdx.x / Dn, d = threadIdx.x % Dn;
+    if (slot >= S) return;
+    const size_t prow = (size_t)a.plane_P * a.plane_stride; // dwords of one clause's planes
+    for (int64_t c = u.c0 + slot; c < u.c1; c += S) {
+        uint32_t code[KMAX], x[KMAX];
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) code[q] = q < k ? codes[c * k + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) x[q] = q < k ? lit_dword<false>(a.bits32, code[q], a.W2, d) : 0u;
+        uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0; // R < 16
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            const uint32_t c0 = r0 & x[q];
+            r0 ^= x[q];
+            const uint32_t c1 = r1 & c0;
+            r1 ^= c0;
+            const uint32_t c2 = r2 & c1;
+            r2 ^= c1;
+            r3 ^= c2;
+        }
+        uint32_t* P = a.planes + (size_t)(base + c) * prow + d;
+        P[0] = r0;
+        P[(size_t)a.plane_stride] = r1;
+        P[(size_t)2 * a.plane_stride] = r2;
+        P[(size_t)3 * a.plane_stride] = r3;
+    }
+}
+
+template <int J, int KT>
+__global__ __launch_bounds__(256) void planes_hist_kernel(FwdArgs a, int nunits)
+{
+    if (a.ctrl && a.ctrl->stop) return;
+    constexpr int P = 4, Q = P * J / 2; // 16-byte loads per clause
+    __shared__ uint32_t s_cnt[J][KT + 1][64]; // the block's counts, summed over its waves
+    const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
+    const int K1 = a.K1;
+    uint32_t cnt[J][KT + 1]; // [j][0]: clauses; [j][r]: clauses with R >= r
+    int32_t inst = -1;
+    for (int e = threadIdx.x; e < J * (KT + 1) * 64; e += 256) (&s_cnt[0][0][0])[e] = 0;
+    __syncthreads();
+    auto flush = [&](int32_t to) {
+        // every wave of the block reaches each flush together: the units
+        // of a block are visited in the same order by all its waves
+        if (inst >= 0) {
+#pragma unroll
+            for (int j = 0; j < J; ++j)
+#pragma unroll
+                for (int r = 0; r <= KT; ++r) atomicAdd(&s_cnt[j][r][lane], cnt[j][r]);
+        }
+        __syncthreads();
+        if (inst >= 0) {
+            uint32_t* H = a.H + (size_t)inst * a.H_stride;
+            for (int e = threadIdx.x; e < J * 64; e += 256) {
+                const int j = e / 64, l = e % 64;
+                const uint32_t cand = 64u * j + l;
+                if ((int)(cand >> 5) >= a.Dn) continue;
+#pragma unroll
+                for (int r = 0; r <= KT; ++r) {
+                    if (r >= K1) break;
+                    const uint32_t h = s_cnt[j][r][l] - (r < KT ? s_cnt[j][r + 1][l] : 0u);
+                    if (h) atomicAdd(&H[(size_t)cand * K1 + r], h);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < J * (KT + 1) * 64; e += 256) (&s_cnt[0][0][0])[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int r = 0; r <= KT; ++r) cnt[j][r] = 0;
+        inst = to;
+    };
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int r = 0; r <= KT; ++r) cnt[j][r] = 0;
+    for (int un = blockIdx.x; un < nunits; un += gridDim.x) { // block-uniform
+        const FwdUnit u = a.units[un];
+        if (a.ictrl && a.ictrl[u.inst].frozen) continue;
+        if (u.inst != inst) flush(u.inst);
+        const int k = u.pad;
+        const int64_t base = a.wide_base[k];
+        for (int64_t c = u.c0 + 64 * (int64_t)wv; c < u.c1; c += 256) { // wave-uniform
+            const int64_t rec = c + lane;
+            const bool ok = rec < u.c1;
+            const uint4* pl = (const uint4*)a.planes + (size_t)(base + (ok ? rec : c)) * Q;
+            uint64_t wd[P * J];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const uint4 v = ok ? pl[q] : make_uint4(0u, 0u, 0u, 0u);
+                wd[2 * q] = ((uint64_t)v.y << 32) | v.x;
+                wd[2 * q + 1] = ((uint64_t)v.w << 32) | v.z;
+            }
+            const uint32_t n = (uint32_t)((u.c1 - c) < 64 ? (u.c1 - c) : 64);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                uint64_t pw[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) pw[p] = transpose64(wd[p * J + j], lane);
+                uint64_t ge[KT];
+                thermometer<P, KT>(pw, ge);
+                cnt[j][0] += n;
+#pragma unroll
+                for (int r = 0; r < KT; ++r) cnt[j][r + 1] += (uint32_t)__popcll(ge[r]);
+            }
+        }
+    }
+    flush(-1);
 }
 
 // ---------------------------------------------------------------------------
@@ -2479,9 +2650,30 @@ static hipError_t launch_fwd_vr(const FwdArgs& a, dim3 grid, hipStream_t st)
     }
 }
 
-// every wide bucket (widths 5 .. kmax) in one launch: a.KW = 0, unit widths in pad
+// every wide bucket (widths 5 .. kmax) in one launch: a.KW = 0, unit widths in
+// pad.  With clause planes (four per clause, kmax <= 15): the planes pass,
+// then the histogram pass over the planes; else the lane-per-candidate kernel.
 hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st)
 {
+    if (a.planes && a.plane_P == 4 && kmax <= 15 && a.Dn <= 8) {
+        if (kmax <= 8) hipLaunchKernelGGL((fwd_planes_kernel<8>), dim3((unsigned)nunits), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((fwd_planes_kernel<15>), dim3((unsigned)nunits), dim3(256), 0, st, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int J = a.plane_stride / 2; // words per plane row
+        const unsigned hb = (unsigned)std::min(nunits, 256);
+        if (J == 1) {
+            if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<1, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
+            else hipLaunchKernelGGL((planes_hist_kernel<1, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
+        } else if (J == 2) {
+            if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<2, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
+            else hipLaunchKernelGGL((planes_hist_kernel<2, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
+        } else {
+            if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<4, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
+            else hipLaunchKernelGGL((planes_hist_kernel<4, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)nunits, (unsigned)tiles, 1);
     const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
     if (kmax <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4, false>), grid, dim3(256), lds, st, a);
@@ -2675,7 +2867,7 @@ static hipError_t launch_pair_k(const VarArgs& a, int op, int blocks, hipStream_
 }
 
 // two variables per wave: window gather, rows of at most 32 candidates
-static bool pair_rows(const VarArgs& a) { return a.window && a.N <= 32; }
+static bool pair_rows(const VarArgs& a) { return a.window && a.N <= 32 && !a.lit_rows; }
 
 template <int J, int KW, bool FULL>
 static hipError_t launch_plane_jkf(const VarArgs& a, int op, int blocks, hipStream_t st)

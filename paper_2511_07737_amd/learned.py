@@ -284,6 +284,87 @@ def compare(weights: np.ndarray, V: int = 100_000, ratio: float = 4.1, restarts:
                 random=summary("random"), majority=summary("majority"), learned=summary("learned"), runs=runs)
 
 
+def censored_percentile(values, n_total: int, q: float):
+    """q-th percentile over n_total runs of which only len(values) have an
+    observed value (the others ran past the cap: larger than every observed
+    value); None when that order statistic is censored."""
+    if n_total <= 0:
+        return None
+    k = max(1, int(np.ceil(q / 100.0 * n_total)))
+    xs = np.sort(np.asarray(values, dtype=np.float64))
+    return float(xs[k - 1]) if k <= xs.size else None
+
+
+HELDOUT_CHECKPOINTS = (0, 25, 50, 100, 150, 200, 400, 800, 1600, 2400, 3600)
+
+
+def evaluate_heldout(weights: np.ndarray, count: int = 20, V: int = 100_000, ratio: float = 4.1,
+                     restarts: int = 128, max_steps: int = 3600, seed0: int = 20_000, init_seed: int = 1,
+                     params=None, checkpoints=HELDOUT_CHECKPOINTS, device: int = 0) -> dict:
+    """The random, majority-vote and learned starts on `count` held-out
+    planted 3-SAT instances (V variables, ratio*V clauses, seeds seed0 + j),
+    solved as one batch per arm: every instance freezes on its first
+    satisfying candidate.  Per arm: steps and time to all-SAT (the learned
+    arm's time includes its features and network, shared equally by the
+    instances), censored at the step cap; steps to the 99% hand-off; and the
+    lowest unsatisfied-clause count reached by each checkpoint (median over
+    the instances)."""
+    params = params or solve_params()
+    C = int(round(ratio * V))
+    cnfs = [gen.planted_ksat(V, C, 3, seed=seed0 + j) for j in range(count)]
+    cps = sorted(set(int(c) for c in checkpoints if 0 <= c <= max_steps) | {max_steps})
+    out = dict(workload=f"{count} held-out planted 3-SAT instances V={V}, C={C} (seeds {seed0}..{seed0 + count - 1}), "
+                        f"{restarts} restarts, none-mode tau={params.tau}, cap {max_steps} steps, one batch per arm",
+               checkpoints=cps)
+    for arm in ARMS:
+        s = tsat.Solver(device=device, params=params)
+        s.load_batch(cnfs)
+        net = None
+        t0 = time.perf_counter()
+        if arm == "random":
+            s.init_batch(restarts, seed=init_seed)
+        elif arm == "majority":
+            s.init_from_proposal(restarts, seed=init_seed, p_true=majority_proposal(cnfs))
+        else:
+            net = tsat.Mlp(weights, device=device)
+            s.propose(net, want_host=False)
+            s.init_from_proposal(restarts, seed=init_seed)
+        sat0, _ = s.check()  # synchronizes: the start is in place
+        t_start = time.perf_counter() - t0
+        unsat = C - sat0.reshape(count, restarts).max(axis=1)
+        best = unsat.astype(np.int64).copy()
+        curve = [float(np.median(best))]
+        s.set_graph(True)
+        done = 0
+        for cp in cps[1:]:
+            s.step(cp - done, stop_on_sat=True)
+            done = cp
+            st = s.instance_status()
+            now = np.array([0 if x["first_sat_step"] >= 0 else x["num_clauses"] - x["best_sat_count"] for x in st])
+            best = np.minimum(best, now)
+            curve.append(float(np.median(best)))
+            log(f"{arm}: step {cp}, solved {sum(x['first_sat_step'] >= 0 for x in st)}/{count}, "
+                f"median best unsat {curve[-1]:.0f}")
+        st = s.instance_status()
+        hz = s.device_clock_hz()
+        share = t_start / count if arm != "random" else 0.0
+        sat_steps = [x["first_sat_step"] for x in st if x["first_sat_step"] >= 0]
+        sat_times = [(x["sat_ticks"] - x["start_ticks"]) / hz + share for x in st if x["first_sat_step"] >= 0]
+        s99 = [x["first_converged_step"] for x in st if x["first_converged_step"] >= 0]
+        if net is not None:
+            net.close()
+        s.close()
+        out[arm] = dict(
+            solved=len(sat_steps), instances=count, censored=len(sat_steps) < count,
+            p50_steps_to_sat=censored_percentile(sat_steps, count, 50),
+            p90_steps_to_sat=censored_percentile(sat_steps, count, 90),
+            p50_time_to_sat_s=censored_percentile(sat_times, count, 50),
+            reached_99=len(s99), p50_steps_to_99=censored_percentile(s99, count, 50),
+            median_start_unsat=float(np.median(unsat)), start_s=t_start,
+            min_unsat_vs_step=curve)
+    return out
+
+
 def compare_batch(weights: np.ndarray, count: int = 400, vmin: int = 200, vmax: int = 1000, ratio: float = 4.0,
                   restarts: int = 32, max_steps: int = 3000, seed: int = 770_000, params=None,
                   device: int = 0) -> dict:

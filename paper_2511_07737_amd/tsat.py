@@ -140,6 +140,8 @@ _SIGS = [
     ("tsat_set_timing", _i32, [_P, _i32]),
     ("tsat_get_timing", _i32, [_P, ct.POINTER(_f64), ct.POINTER(_i32)]),
     ("tsat_copy_calibrate", _i32, [_P, _i64, ct.POINTER(_f64)]),
+    ("tsat_stream_calibrate", _i32, [_P, _i64, _i32, _i32, ct.POINTER(_f64)]),
+    ("tsat_set_literal_rows", _i32, [_P, _i32]),
     ("tsat_get_launch_config", _i32, [_P, ct.POINTER(LaunchConfig)]),
     ("tsat_set_launch_config", _i32, [_P, ct.POINTER(LaunchConfig)]),
     ("tsat_autotune", _i32, [_P, _i32, _P, ct.POINTER(LaunchConfig), ct.POINTER(_i32)]),
@@ -241,6 +243,8 @@ class Solver:
         self._h = h
         self.V = 0
         self.N = 0
+        self._lit_rows = 0  # requested for the next batch
+        self.rows = 0       # logit rows of the current batch (V, or 2V with literal rows)
 
     # lifecycle ----------------------------------------------------------
     def close(self):
@@ -270,6 +274,7 @@ class Solver:
         _check(lib().tsat_load_cnf(self._h, int(num_vars), int(s.size), _ptr(s)))
         self.V = int(num_vars)
         self.N = 0
+        self._lit_rows = 0
 
     def load(self, cnf) -> None:
         """Load a ``gen.CNF``."""
@@ -280,6 +285,7 @@ class Solver:
         V, _ = dimacs_read(path)
         self.V = V
         self.N = 0
+        self._lit_rows = 0
 
     def load_batch(self, cnfs) -> None:
         """Load a list of ``gen.CNF`` instances as one batch."""
@@ -291,6 +297,7 @@ class Solver:
         _check(lib().tsat_load_cnf_batch(self._h, len(cnfs), _ptr(nv), _ptr(off), _ptr(lits)))
         self.V = int(lib().tsat_num_vars(self._h))
         self.N = 0
+        self._lit_rows = 0
 
     @property
     def num_instances(self) -> int:
@@ -320,14 +327,22 @@ class Solver:
     def max_width(self) -> int:
         return int(lib().tsat_max_width(self._h))
 
+    def set_literal_rows(self, enable: bool) -> None:
+        """Independent literal rows (2V logit rows) from the next init_batch on."""
+        _check(lib().tsat_set_literal_rows(self._h, int(bool(enable))))
+        self._lit_rows = int(bool(enable))
+        self.N = 0
+
     def init_batch(self, n: int, seed: int = 0, init_logits: np.ndarray | None = None) -> None:
+        rows = (2 if self._lit_rows else 1) * self.V
         lg = None
         if init_logits is not None:
             lg = np.ascontiguousarray(init_logits, dtype=np.float32)
-            if lg.shape != (self.V, n):
-                raise ValueError(f"init_logits must have shape {(self.V, n)}")
+            if lg.shape != (rows, n):
+                raise ValueError(f"init_logits must have shape {(rows, n)}")
         _check(lib().tsat_init_batch(self._h, int(n), int(seed) & ((1 << 64) - 1), _ptr(lg)))
         self.N = int(n)
+        self.rows = rows
 
     # launch shapes -------------------------------------------------------
     def launch_config(self) -> LaunchConfig:
@@ -380,6 +395,7 @@ class Solver:
                 raise ValueError(f"p_true must have shape {(self.V,)}")
         _check(lib().tsat_init_from_proposal(self._h, int(n), int(seed) & ((1 << 64) - 1), _ptr(pp)))
         self.N = int(n)
+        self.rows = self.V
 
     # solving ------------------------------------------------------------
     def step(self, max_steps: int = 1, params: Params | None = None, stop_on_sat: bool | int = False,
@@ -438,7 +454,7 @@ class Solver:
         _check(lib().tsat_set_logits(self._h, _ptr(t)))
 
     def get_logits(self) -> np.ndarray:
-        out = np.empty((self.V, self.N), dtype=np.float32)
+        out = np.empty((self.rows, self.N), dtype=np.float32)
         _check(lib().tsat_get_logits(self._h, _ptr(out)))
         return out
 
@@ -449,7 +465,7 @@ class Solver:
         _check(lib().tsat_set_state(self._h, _ptr(th), _ptr(mm), _ptr(vv), int(t)))
 
     def get_state(self):
-        th = np.empty((self.V, self.N), dtype=np.float32)
+        th = np.empty((self.rows, self.N), dtype=np.float32)
         m = np.empty_like(th)
         v = np.empty_like(th)
         t = _i64()
@@ -465,7 +481,8 @@ class Solver:
         _check(lib().tsat_set_adam_origin(self._h, int(origin)))
 
     def get_bits(self) -> np.ndarray:
-        out = np.empty((self.V, (self.N + 63) // 64), dtype=np.uint64)
+        """Value rows [V][W], or every literal row [2V][W] with literal rows on."""
+        out = np.empty((self.rows, (self.N + 63) // 64), dtype=np.uint64)
         _check(lib().tsat_get_bits(self._h, _ptr(out)))
         return out
 
@@ -482,7 +499,7 @@ class Solver:
         return hist, S, float(loss.value)
 
     def get_grad(self, params: Params | None = None):
-        U = np.empty((self.V, self.N), dtype=np.float32)
+        U = np.empty((self.rows, self.N), dtype=np.float32)
         g = np.empty_like(U)
         _check(lib().tsat_get_grad(self._h, ct.byref(params) if params is not None else None, _ptr(U), _ptr(g)))
         return U, g
@@ -529,6 +546,14 @@ class Solver:
         it = _i32()
         _check(lib().tsat_get_timing(self._h, ms, ct.byref(it)))
         return list(ms), int(it.value)
+
+    def stream_calibrate(self, nbytes: int, kind: int, reps: int = 10) -> float:
+        """Average ms of a bandwidth reference kernel over arrays of nbytes
+        (kind 0: copy; 1: three arrays in place, 16-byte accesses; 2: the same
+        with the update kernels' 4-byte row pattern)."""
+        ms = _f64()
+        _check(lib().tsat_stream_calibrate(self._h, int(nbytes), int(kind), int(reps), ct.byref(ms)))
+        return float(ms.value)
 
     def copy_calibrate(self, nbytes: int) -> float:
         """Run one plain device copy of nbytes (read + write); returns its ms."""
