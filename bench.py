@@ -92,8 +92,10 @@ def implementation_bytes(cnf, N, planes):
     J = W if W <= 2 else (4 if W <= 4 else 8 * ((W + 7) // 8))
     out = dict(means_offsets=24 * V, complement_rows=V * W * 8)
     if planes:
-        P = 2 if int(cnf.widths().max()) <= 3 else 4
-        out["planes_write"] = out["planes_read"] = int(C * P * J * 8)
+        # two planes per clause of width <= 3, four per wider clause
+        w = cnf.widths()
+        rows = 2 * int((w <= 3).sum()) + 4 * int((w > 3).sum())
+        out["planes_write"] = out["planes_read"] = int(rows * J * 8)
     else:
         occ_words = int((cnf.widths().astype(np.int64) ** 2).sum())
         out["occurrence_records"] = 4 * occ_words
@@ -155,6 +157,54 @@ def learned_vs_random():
     res["small_batch"] = learned.compare_batch(weights, count=400, vmin=200, vmax=1000, ratio=4.0)
     res["training"] = {k: meta.get(k) for k in ("instances", "rows", "val_accuracy", "final_loss", "epochs")}
     return res
+
+
+def mixing_block():
+    """Assignment mixing at the learning-rate restarts (every 360 iterations)
+    against the plain schedule, none-mode tau = 2: the tiny configuration
+    (32 instances, 1500 iterations, freeze on SAT: solved count and steps to
+    SAT) and the large one (2000 iterations: steps to the 99% hand-off and
+    the best candidate's unsatisfied clauses at the end and at each
+    restart)."""
+    import numpy as np
+
+    from paper_2511_07737_amd import gen, tsat
+
+    print("[bench] mixing at restarts", file=sys.stderr, flush=True)
+    out = {}
+    cnfs = [gen.planted_ksat(200, 800, 3, seed=j) for j in range(1, 33)]
+    th = np.concatenate([gen.normal_logits(200, 64, 1000 + j) for j in range(1, 33)])
+    tiny = {"workload": "32 planted 3-SAT instances V=200, C=800, N=64, 1500 iterations, none-mode tau=2"}
+    for mix in (0, 1):
+        s = tsat.Solver(params=tsat.default_params(norm_mode=tsat.MODE_NONE, tau=2.0, mix=mix))
+        s.load_batch(cnfs)
+        s.init_batch(64, init_logits=th)
+        s.set_graph(True)
+        s.step(1500, stop_on_sat=True)
+        sat = np.array([x["first_sat_step"] for x in s.instance_status()])
+        s.close()
+        q = [float(v) for v in np.percentile(sat[sat >= 0], [10, 50, 90])] if (sat >= 0).any() else None
+        tiny["mix" if mix else "plain"] = {"solved": int((sat >= 0).sum()), "steps_to_sat_p10_p50_p90": q,
+                                            "solved_after_360": int((sat >= 360).sum())}
+    out["tiny"] = tiny
+    cnf = gen.planted_ksat(1_000_000, 4_100_000, 3, seed=1)
+    th = gen.normal_logits(cnf.num_vars, 256, 1001)
+    large = {"workload": "planted 3-SAT V=1e6, C=4.1e6, N=256, 2000 iterations, none-mode tau=2"}
+    for mix in (0, 1):
+        s = tsat.Solver(params=tsat.default_params(norm_mode=tsat.MODE_NONE, tau=2.0, mix=mix))
+        s.load(cnf)
+        s.init_batch(256, init_logits=th)
+        best = []
+        done, first99 = 0, -1
+        for stop in (360, 720, 1080, 1440, 1800, 2000):
+            r = s.step(stop - done)
+            done = stop
+            first99 = r.first_converged_step
+            best.append(int(cnf.num_clauses - r.best_sat_count))
+        s.close()
+        large["mix" if mix else "plain"] = {"steps_to_99": first99, "best_unsat_at_360_720_1080_1440_1800_2000": best}
+    out["large"] = large
+    return out
 
 
 def ragged_block(count, max_steps):
@@ -433,6 +483,7 @@ def main():
     if not args.no_learned:
         out["tiny"] = tiny_distribution()
         out["learned_vs_random"] = learned_vs_random()
+        out["mixing"] = mixing_block()
     if not args.no_ragged:
         out["ragged"] = ragged_block(args.ragged_count, args.ragged_steps)
     if not args.no_cpu_baseline:

@@ -353,6 +353,18 @@ int32_t tsat_fwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
 int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, const float* dS, float* U,
                      void* stream);
 
+/* The same backward by the clause-major design the library does not use for
+ * its step: one thread per (clause, 32 candidates) computes R and adds the
+ * dL/dR table entry into every literal's row of U with FP32 atomics (the
+ * first literal of each clause into an LDS tile of the block, flushed with
+ * atomics at the end).  U is zeroed first.  Kept as the measured comparison
+ * point of the variable-major gather; the order of the atomic additions is
+ * not fixed, so results may differ from run to run in the last bits (each
+ * U entry within (degree + 1) * 2^-24 of the sum of its terms' magnitudes).
+ * Single-instance solvers, N <= 256; E_ARG / E_STATE as tsat_bwd_dev. */
+int32_t tsat_bwd_scatter_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, const float* dS, float* U,
+                             void* stream);
+
 /* The differentiable path of Fig. 3 on caller logits theta (device [V][N]
  * float, the real-valued assignment matrix; N <= TSAT_MAX_STEP_N), for a
  * single-instance solver; mode is TSAT_MODE_MEAN (Eq. 5 normalization

@@ -77,6 +77,8 @@ struct FwdArgs {
     int32_t plane_P;        // planes per clause (2 or 4)
     int64_t plane_base;     // global index of the bucket's first clause
     int32_t vrows;          // bits32 holds value rows only ([V][W2]); not-x is the complement
+    int32_t nunits;         // work units of the launch
+    int32_t xcd;            // XCD-aware unit order (grid rounded up to a multiple of 8)
     // KW = 0 (wide-clause kernel): the units of every wide bucket in one
     // launch; a unit's width is in its pad field
     const uint32_t* wide_codes[TSAT_MAX_WIDTH + 1];
@@ -113,6 +115,7 @@ struct VarArgs {
                               // carry no header; 0: generic records
     int32_t group;            // records per scalar-load group in the pure kernel
     int32_t window;           // clause-plane gather by 64-record windows (vector loads, transposed)
+    int32_t xcd;              // XCD-aware order of the variable chunks
     const uint32_t* occ_off;  // [V+1] offsets into occ_data (words, or records if pure)
     const uint32_t* occ_mid;  // [V] first record of negative occurrences
     const uint32_t* occ_data; // records: [k-1,] the other k-1 literal indices
@@ -141,6 +144,7 @@ struct VarArgs {
     // occ_mid), and the forward pass's planes of R for these bits
     const uint32_t* occ_cid;  // null: gather the other literals' rows instead
     const uint32_t* planes;   // [clauses][P][2 J] dwords
+    uint32_t narrow_end;      // clauses below this global index hold 2 planes, the rest 4 (after them)
     const uint32_t* cid_off;  // [V+1] record offsets of occ_cid
     const uint32_t* cid_mid;  // [V] first record of negative occurrences
     // generic stores: variables with many occurrence words are split into
@@ -169,6 +173,8 @@ struct SelectArgs {
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st);
 hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st);
 hipError_t launch_smin(const SminArgs& a, hipStream_t st);
+hipError_t launch_adj_scatter(const uint32_t* codes, int64_t Cb, int k, int N, int K1, const uint32_t* bits32,
+                              int W2, const float* tbl, float* U, int V, hipStream_t st);
 hipError_t launch_fwd_units(FwdUnit* u, int64_t n, int64_t per, int64_t Cb, hipStream_t st);
 // device address of the allocation-free entry point's fixed scratch array on
 // `device` (which must be current); looked up once per device

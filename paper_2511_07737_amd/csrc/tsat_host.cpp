@@ -90,6 +90,8 @@ struct tsat_solver {
     int32_t pure_group = 2;           // records per load group, uniform-width stores
     int32_t clause_planes = 1;        // uniform widths 2, 3: backward gathers the forward's planes of R
     int32_t window_gather = 1;        // clause planes: 64 records per vector load, transposed across the wave
+    int32_t xcd_order = 1;            // XCD-aware order of the forward's work units
+    int32_t xcd_update = 0;           // XCD-aware order of the update's variable chunks
 
     // forward work units of all wide buckets (widths > 4) in one launch, per clauses-per-wave
     std::map<int, std::pair<DBuf*, int>> wide_units;
@@ -253,10 +255,18 @@ static bool plane_path(const tsat_solver* s, int32_t N)
 }
 
 // Planes of R for N candidates: [clauses][P][2 J] dwords, zeroed when (re)allocated.
+// Clauses of widths 1 .. 3 come first in the global clause order and hold
+// two planes each (R <= 3); the wider ones follow with four.
+static int64_t narrow_end(const tsat_solver* s)
+{
+    return s->st.K >= 4 ? s->st.plane_base[4] : s->st.plane_clauses;
+}
+
 static int32_t ensure_planes(tsat_solver* s, DBuf& buf, int32_t N, hipStream_t st)
 {
-    const size_t P = (size_t)planes_for_width(s->st.K);
-    const size_t bytes = std::max<size_t>(16, (size_t)s->st.plane_clauses * P * 8 * (size_t)row_words((N + 63) / 64));
+    const size_t G3 = (size_t)narrow_end(s);
+    const size_t words = G3 * 2 + ((size_t)s->st.plane_clauses - G3) * 4; // plane rows
+    const size_t bytes = std::max<size_t>(16, words * 8 * (size_t)row_words((N + 63) / 64));
     if (buf.p && buf.bytes >= bytes) return TSAT_OK;
     RET(buf.alloc(bytes, "clause planes"));
     HIPCHK(launch_fill_u32(buf.as<uint32_t>(), (int64_t)(bytes / 4), 0u, st));
@@ -320,10 +330,14 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
     base.H_stride = (int64_t)64 * W * base.K1;
     base.ctrl = ctrl;
     base.ictrl = ictrl;
+    // narrow clauses (widths 1 .. 3): two planes each from the start of the
+    // plane buffer; wider ones: four planes each after them
+    const int64_t G3 = with_planes ? narrow_end(s) : 0;
+    uint32_t* wide_planes = nullptr;
     if (with_planes) {
         base.planes = planes;
         base.plane_stride = 2 * row_words(W);
-        base.plane_P = planes_for_width(s->st.K);
+        wide_planes = planes + (size_t)G3 * 2 * base.plane_stride;
     }
     // widths 1 .. 4: one launch per bucket
     for (auto* b : s->buckets) {
@@ -338,7 +352,14 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
         a.Dn = g.Dn;
         a.DT = g.DT;
         a.CPT = g.CPT;
-        if (with_planes) a.plane_base = s->st.plane_base[b->k];
+        if (with_planes) {
+            const bool narrow = b->k <= 3;
+            a.planes = narrow ? planes : wide_planes;
+            a.plane_P = narrow ? 2 : 4;
+            a.plane_base = s->st.plane_base[b->k] - (narrow ? 0 : G3);
+        }
+        a.nunits = nunits;
+        a.xcd = s->xcd_order;
         HIPCHK(launch_fwd(a, nunits, g.tiles, st));
     }
     // wider clauses: every bucket in one launch
@@ -352,11 +373,17 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
         a.Dn = g.Dn;
         a.DT = g.DT;
         a.CPT = g.CPT;
+        if (with_planes) {
+            a.planes = wide_planes;
+            a.plane_P = 4;
+        }
         for (auto* b : s->buckets) {
             if (b->k <= 4 || b->count == 0) continue;
             a.wide_codes[b->k] = b->codes.as<uint32_t>();
-            if (with_planes) a.wide_base[b->k] = s->st.plane_base[b->k];
+            if (with_planes) a.wide_base[b->k] = s->st.plane_base[b->k] - G3;
         }
+        a.nunits = nunits;
+        a.xcd = s->xcd_order;
         if (nunits > 0) HIPCHK(launch_fwd_wide(a, kmax, nunits, g.tiles, st));
     }
     return TSAT_OK;
@@ -409,6 +436,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.group = s->pure_group;
     // the window gather keeps its counts in 16-bit halves
     a.window = s->window_gather && s->st.max_sign_rec < 65536;
+    a.xcd = s->xcd_update;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
     a.occ_data = s->occ_data.as<uint32_t>();
@@ -421,6 +449,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     // clause-plane gather: evaluations write their planes to planes_scr, the
     // step overrides this with its own buffer
     a.occ_cid = plane_path(s, N) ? s->occ_cid.as<uint32_t>() : nullptr;
+    a.narrow_end = s->loaded && s->occ_cid.p ? (uint32_t)narrow_end(s) : 0u;
     a.cid_off = s->cid_off.p ? s->cid_off.as<uint32_t>() : a.occ_off;
     a.cid_mid = s->cid_mid.p ? s->cid_mid.as<uint32_t>() : a.occ_mid;
     a.planes = s->planes_scr.as<uint32_t>();
@@ -604,6 +633,8 @@ int32_t tsat_create(const tsat_config* cfg, tsat_solver** out)
     s->pure_group = env_int("TSAT_PURE_GROUP", s->pure_group);
     s->clause_planes = env_int("TSAT_CLAUSE_PLANES", s->clause_planes) != 0;
     s->window_gather = env_int("TSAT_WINDOW_GATHER", s->window_gather) != 0;
+    s->xcd_order = env_int("TSAT_XCD_ORDER", s->xcd_order) != 0;
+    s->xcd_update = env_int("TSAT_XCD_UPDATE", s->xcd_update) != 0;
     if (cfg && cfg->stream) {
         s->stream = (hipStream_t)cfg->stream;
     } else {
@@ -1556,6 +1587,31 @@ int32_t tsat_bwd_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau,
     return TSAT_OK;
 }
 
+int32_t tsat_bwd_scatter_dev(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, const float* dS, float* U,
+                             void* stream)
+{
+    g_err.clear();
+    if (!s) return fail(TSAT_E_ARG, "solver is NULL");
+    if (!s->loaded) return fail(TSAT_E_STATE, "no CNF loaded");
+    if (N < 1 || N > 256 || !bits || !dS || !U || !(tau >= 0.f)) return fail(TSAT_E_ARG, "invalid arguments");
+    RET(set_dev(s));
+    hipStream_t st = (hipStream_t)stream; // NULL: the null (default) stream
+    const int32_t W = (N + 63) / 64, Np = 64 * W;
+    if ((size_t)K1_of(s) * Np * 4 > 48 * 1024) return fail(TSAT_E_ARG, "table exceeds 48 KiB");
+    RET(dev_prepare(s, bits, N, st));
+    tsat_params p = s->params;
+    p.tau = tau;
+    RET(eval_rows(s, p, s->lits_scr.as<uint64_t>(), N, dS, nullptr, nullptr, nullptr, nullptr, s->table_scr.as<float>(), st));
+    HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(U), (int64_t)s->st.V * N, 0u, st));
+    for (auto* b : s->buckets) {
+        if (b->count == 0 || b->k == 0) continue;
+        HIPCHK(launch_adj_scatter(b->codes.as<uint32_t>(), b->count, b->k, N, K1_of(s),
+                                  reinterpret_cast<const uint32_t*>(s->lits_scr.p), 2 * W, s->table_scr.as<float>(), U,
+                                  s->st.V, st));
+    }
+    return TSAT_OK;
+}
+
 int32_t tsat_fwd_dev_noalloc(tsat_solver* s, const uint64_t* bits, int32_t N, float tau, float* S, uint32_t* hist,
                              void* stream)
 {
@@ -1606,6 +1662,7 @@ int32_t tsat_fwd_dev_noalloc(tsat_solver* s, const uint64_t* bits, int32_t N, fl
         a.CPT = g.CPT;
         a.H = H;
         a.H_stride = (int64_t)Np * K1;
+        a.nunits = (int32_t)nunits;
         HIPCHK(launch_fwd(a, (int)nunits, g.tiles, st));
     }
     tsat_params p = s->params;

@@ -112,6 +112,44 @@ __device__ __forceinline__ double half_sum(double x)
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
+// XCD-aware work order.  Workgroups are handed to the eight XCDs round-robin
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2.  With `on`
+// and a grid that is a multiple of 8, each XCD takes a contiguous eighth of
+// the work items, so items that touch the same data (consecutive clauses of
+// one instance or community, consecutive variables) share that XCD's L2.
+// Without it (or for other grid sizes) the items go round-robin as before.
+struct ItemRange {
+    uint32_t first, end, stride;
+};
+
+__device__ __forceinline__ ItemRange xcd_items(bool on, uint32_t nitems, uint32_t per_block, uint32_t slot)
+{
+    ItemRange r;
+    const uint32_t g = gridDim.x;
+    if (on && g % 8u == 0u) {
+        const uint32_t x = blockIdx.x % 8u, local = blockIdx.x / 8u;
+        const uint32_t share = (nitems + 7u) / 8u;
+        const uint32_t b0 = x * share;
+        r.first = b0 + local * per_block + slot;
+        r.end = b0 + share < nitems ? b0 + share : nitems;
+        r.stride = (g / 8u) * per_block;
+    } else {
+        r.first = blockIdx.x * per_block + slot;
+        r.end = nitems;
+        r.stride = g * per_block;
+    }
+    return r;
+}
+
+// The forward work unit of this block (grid rounded up to a multiple of 8
+// when XCD-aware; surplus blocks get an index >= n and return).
+__device__ __forceinline__ uint32_t xcd_unit(bool on, uint32_t n)
+{
+    const uint32_t g = gridDim.x;
+    if (!on || g % 8u != 0u) return blockIdx.x;
+    return (blockIdx.x % 8u) * (g / 8u) + blockIdx.x / 8u;
+}
+
 // ---------------------------------------------------------------------------
 // Forward: R = P A (Eq. 1) as a per-candidate histogram of R.
 //
@@ -137,7 +175,9 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
 {
     extern __shared__ uint32_t lh[]; // [DT*32][KW+1]
     if (a.ctrl && a.ctrl->stop) return;
-    const FwdUnit u = a.units[blockIdx.x];
+    const uint32_t un = xcd_unit(a.xcd, (uint32_t)a.nunits);
+    if (un >= (uint32_t)a.nunits) return;
+    const FwdUnit u = a.units[un];
     if (a.ictrl && a.ictrl[u.inst].frozen) return;
     uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
     const int tid = threadIdx.x;
@@ -169,7 +209,7 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
                 for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x;
                 ge[0] |= x;
             }
-            if (!VR && a.planes) {
+            if (a.planes) {
                 // R in binary for the backward, plane_P planes: bit p of R is
                 // the parity of the masks [R >= m 2^p], m >= 1
                 uint32_t* P = a.planes + (size_t)(a.plane_base + c) * (size_t)(a.plane_P * a.plane_stride) + d;
@@ -235,7 +275,9 @@ __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
 {
     extern __shared__ uint32_t lh[]; // [4 waves][64 lanes][K1]
     if (a.ctrl && a.ctrl->stop) return;
-    const FwdUnit u = a.units[blockIdx.x];
+    const uint32_t un = xcd_unit(a.xcd, (uint32_t)a.nunits);
+    if (un >= (uint32_t)a.nunits) return;
+    const FwdUnit u = a.units[un];
     if (a.ictrl && a.ictrl[u.inst].frozen) return;
     uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
     const uint32_t lane = __lane_id(), wave = threadIdx.x / 64u;
@@ -270,7 +312,7 @@ __global__ __launch_bounds__(256) void fwd_hist_lanes_kernel(FwdArgs a)
 #pragma unroll
             for (int q = 0; q < KMAX; ++q) R += (x[g][q] >> bit) & 1u;
             if (live) atomicAdd(&my[R], 1u);
-            if (!VR && a.planes) {
+            if (a.planes) {
                 // R in binary for the backward: plane p of this clause, word
                 // blockIdx.y (the wave's 64 candidates), one bit per lane
                 uint64_t bal[4];
@@ -1632,7 +1674,6 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
     constexpr uint32_t kChunk = 4; // variables per wave work item (measured best of 2, 4, 8, 16)
     const uint32_t lane = __lane_id();
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
-    const uint32_t nwaves = uniform(gridDim.x * 4u);
     const uint32_t V = (uint32_t)a.V;
     const int W = a.W;
     const StepScalars c = load_scalars(a, OP);
@@ -1647,7 +1688,8 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
     int bad = 0;
     const uint32_t nchunks = (V + kChunk - 1) / kChunk;
 
-    for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
+    const ItemRange cr = xcd_items(a.xcd, nchunks, 4u, wave0 % 4u);
+    for (uint32_t ch = cr.first; ch < cr.end; ch += cr.stride) {
         const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
         const uint32_t rend = sload(a.occ_off + ve); // end of the chunk's records
         uint32_t w = 0;                              // window [w, w + 64), once loaded
@@ -1809,7 +1851,6 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
     const uint32_t lane = __lane_id();
     const uint32_t h = lane >> 5, l = lane & 31u;
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
-    const uint32_t nwaves = uniform(gridDim.x * 4u);
     const uint32_t V = (uint32_t)a.V;
     const int N = a.N, Np = a.Np;
     const StepScalars c = load_scalars(a, OP);
@@ -1821,7 +1862,8 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
     int bad = 0;
     const uint32_t nchunks = (V + kChunk - 1) / kChunk;
 
-    for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
+    const ItemRange cr = xcd_items(a.xcd, nchunks, 4u, wave0 % 4u);
+    for (uint32_t ch = cr.first; ch < cr.end; ch += cr.stride) {
         const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
         const uint32_t rend = sload(a.occ_off + ve);
         uint32_t w = 0;
@@ -1987,11 +2029,16 @@ __device__ __forceinline__ void load_window_p(const VarArgs& a, uint32_t w, uint
     const uint32_t rec = w + lane;
     const bool ok = rec < end;
     const uint32_t id = ok ? a.occ_cid[rec] : 0u;
-    const uint4* pl = (const uint4*)a.planes + (size_t)id * Q;
+    // clauses below narrow_end (widths up to 3) hold two planes (the upper
+    // two read as zero), the wider ones four, stored after them
+    const bool narrow = P == 2 || id < a.narrow_end;
+    const uint4* pl = narrow ? (const uint4*)a.planes + (size_t)id * J
+                             : (const uint4*)a.planes + (size_t)a.narrow_end * J + (size_t)(id - a.narrow_end) * Q;
     uint64_t wd[P * J];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        const uint4 q = ok ? pl[k] : make_uint4(0u, 0u, 0u, 0u);
+        const bool ld = ok && (k < J || !narrow);
+        const uint4 q = ld ? pl[k] : make_uint4(0u, 0u, 0u, 0u);
         wd[2 * k] = ((uint64_t)q.y << 32) | q.x;
         wd[2 * k + 1] = ((uint64_t)q.w << 32) | q.z;
     }
@@ -2014,7 +2061,6 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
     constexpr uint32_t kChunk = 4; // variables per wave work item
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
     const uint32_t wave0 = uniform(blockIdx.x * 4u + wv);
-    const uint32_t nwaves = uniform(gridDim.x * 4u);
     const uint32_t V = (uint32_t)a.V;
     const int W = a.W, K1 = a.K1, Np = a.Np;
     const StepScalars c = load_scalars(a, OP);
@@ -2037,7 +2083,8 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
     int bad = 0;
     const uint32_t nchunks = (V + kChunk - 1) / kChunk;
 
-    for (uint32_t ch = wave0; ch < nchunks; ch += nwaves) {
+    const ItemRange cr = xcd_items(a.xcd, nchunks, 4u, wave0 % 4u);
+    for (uint32_t ch = cr.first; ch < cr.end; ch += cr.stride) {
         const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
         const uint32_t rend = sload(a.cid_off + ve);
         uint32_t w = 0;
@@ -2134,11 +2181,13 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
 // the global histogram (integer atomics, so the result is exact).
 // ---------------------------------------------------------------------------
 
-template <int KMAX>
+template <int KMAX, bool VR>
 __global__ __launch_bounds__(256) void fwd_planes_kernel(FwdArgs a)
 {
     if (a.ctrl && a.ctrl->stop) return;
-    const FwdUnit u = a.units[blockIdx.x];
+    const uint32_t un = xcd_unit(a.xcd, (uint32_t)a.nunits);
+    if (un >= (uint32_t)a.nunits) return;
+    const FwdUnit u = a.units[un];
     if (a.ictrl && a.ictrl[u.inst].frozen) return;
     const int k = u.pad;
     const uint32_t* codes = a.wide_codes[k];
@@ -2152,7 +2201,7 @@ __global__ __launch_bounds__(256) void fwd_planes_kernel(FwdArgs a)
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) code[q] = q < k ? codes[c * k + q] : 0u;
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) x[q] = q < k ? lit_dword<false>(a.bits32, code[q], a.W2, d) : 0u;
+        for (int q = 0; q < KMAX; ++q) x[q] = q < k ? lit_dword<VR>(a.bits32, code[q], a.W2, d) : 0u;
         uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0; // R < 16
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) {
@@ -2221,7 +2270,8 @@ __global__ __launch_bounds__(256) void planes_hist_kernel(FwdArgs a, int nunits)
     for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int r = 0; r <= KT; ++r) cnt[j][r] = 0;
-    for (int un = blockIdx.x; un < nunits; un += gridDim.x) { // block-uniform
+    const ItemRange ur = xcd_items(a.xcd, (uint32_t)nunits, 1u, 0u);
+    for (uint32_t un = ur.first; un < ur.end; un += ur.stride) { // block-uniform
         const FwdUnit u = a.units[un];
         if (a.ictrl && a.ictrl[u.inst].frozen) continue;
         if (u.inst != inst) flush(u.inst);
@@ -2253,6 +2303,108 @@ __global__ __launch_bounds__(256) void planes_hist_kernel(FwdArgs a, int nunits)
         }
     }
     flush(-1);
+}
+
+// ---------------------------------------------------------------------------
+// Clause-major adjoint by atomic scatter (the alternative to the
+// variable-major gather of the update kernels, kept for comparison).
+//
+// One thread per (clause, candidate dword) of one width bucket: R of its 32
+// candidates as a bit-sliced binary counter, then for every candidate the
+// table entry dL/dR[R] is added into the row of every literal of the clause
+// (+1 for x_v, -1 for not-x_v: Sec. III-B's straight-through estimator).
+// The block's clauses are consecutive in the lexicographic clause order, so
+// their first (smallest) literals fall into a short run of variables: those
+// contributions go to an LDS tile of ST variable rows (LDS atomics), flushed
+// into U with global atomics at the end; every other contribution is a
+// global FP32 atomic.  U must be zero on entry.
+// ---------------------------------------------------------------------------
+
+struct ScatterArgs {
+    const uint32_t* codes; // [Cb][k]
+    int64_t Cb;
+    int32_t k, N, Np, K1, Dn;
+    const uint32_t* bits32; // literal rows, row stride W2 dwords
+    int32_t W2;
+    const float* tbl;       // [K1][Np]
+    float* U;               // [V][N]
+    int32_t V;
+    int32_t ST;             // variable rows of the LDS tile
+};
+
+__global__ __launch_bounds__(256) void adj_scatter_kernel(ScatterArgs a)
+{
+    extern __shared__ float lds_sc[]; // [K1][Np] table, then [ST][N] tile
+    float* s_tbl = lds_sc;
+    float* s_U = lds_sc + (size_t)a.K1 * a.Np;
+    const int Dn = a.Dn, S = 256 / Dn;
+    const int slot = threadIdx.x / Dn, d = threadIdx.x % Dn;
+    const int64_t c0 = (int64_t)blockIdx.x * S;
+    for (int e = threadIdx.x; e < a.K1 * a.Np; e += 256) s_tbl[e] = a.tbl[e];
+    for (int e = threadIdx.x; e < a.ST * a.N; e += 256) s_U[e] = 0.f;
+    // the tile starts at the first variable of the block's first clause
+    const uint32_t vlo = a.codes[(size_t)c0 * a.k] >> 1;
+    __syncthreads();
+    const int64_t c = c0 + slot;
+    if (slot < S && c < a.Cb) {
+        uint32_t r[6] = {0u, 0u, 0u, 0u, 0u, 0u}; // R <= 32 in binary
+        for (int q = 0; q < a.k; ++q) {
+            const uint32_t code = a.codes[(size_t)c * a.k + q];
+            uint32_t carry = a.bits32[(size_t)code * a.W2 + d];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+                const uint32_t t = r[b] & carry;
+                r[b] ^= carry;
+                carry = t;
+            }
+        }
+        for (int bit = 0; bit < 32; ++bit) {
+            const int i = 32 * d + bit;
+            if (i >= a.N) break;
+            uint32_t R = 0;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) R |= ((r[b] >> bit) & 1u) << b;
+            const float val = s_tbl[(size_t)R * a.Np + i];
+            for (int q = 0; q < a.k; ++q) {
+                const uint32_t code = a.codes[(size_t)c * a.k + q];
+                const uint32_t v = code >> 1;
+                const float x = (code & 1u) ? -val : val;
+                if (q == 0 && v - vlo < (uint32_t)a.ST) atomicAdd(&s_U[(size_t)(v - vlo) * a.N + i], x);
+                else atomicAdd(&a.U[(size_t)v * a.N + i], x);
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < a.ST * a.N; e += 256) {
+        const float x = s_U[e];
+        const uint32_t v = vlo + (uint32_t)(e / a.N);
+        if (x != 0.f && v < (uint32_t)a.V) atomicAdd(&a.U[(size_t)v * a.N + e % a.N], x);
+    }
+}
+
+hipError_t launch_adj_scatter(const uint32_t* codes, int64_t Cb, int k, int N, int K1, const uint32_t* bits32,
+                              int W2, const float* tbl, float* U, int V, hipStream_t st)
+{
+    if (Cb <= 0 || k <= 0) return hipSuccess;
+    ScatterArgs a{};
+    a.V = V;
+    a.codes = codes;
+    a.Cb = Cb;
+    a.k = k;
+    a.N = N;
+    a.Np = 64 * ((N + 63) / 64);
+    a.K1 = K1;
+    a.Dn = (N + 31) / 32;
+    a.bits32 = bits32;
+    a.W2 = W2;
+    a.tbl = tbl;
+    a.U = U;
+    const size_t tbl_bytes = (size_t)K1 * a.Np * 4;
+    a.ST = (int)std::max<size_t>(1, std::min<size_t>(64, (64 * 1024 - tbl_bytes) / ((size_t)N * 4)));
+    const int S = 256 / a.Dn;
+    const size_t lds = tbl_bytes + (size_t)a.ST * N * 4;
+    hipLaunchKernelGGL(adj_scatter_kernel, dim3((unsigned)((Cb + S - 1) / S)), dim3(256), lds, st, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -2650,18 +2802,29 @@ static hipError_t launch_fwd_vr(const FwdArgs& a, dim3 grid, hipStream_t st)
     }
 }
 
+static unsigned fwd_grid_x(const FwdArgs& a, int nunits)
+{
+    return a.xcd ? (unsigned)((nunits + 7) / 8 * 8) : (unsigned)nunits;
+}
+
 // every wide bucket (widths 5 .. kmax) in one launch: a.KW = 0, unit widths in
 // pad.  With clause planes (four per clause, kmax <= 15): the planes pass,
 // then the histogram pass over the planes; else the lane-per-candidate kernel.
 hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st)
 {
     if (a.planes && a.plane_P == 4 && kmax <= 15 && a.Dn <= 8) {
-        if (kmax <= 8) hipLaunchKernelGGL((fwd_planes_kernel<8>), dim3((unsigned)nunits), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((fwd_planes_kernel<15>), dim3((unsigned)nunits), dim3(256), 0, st, a);
+        const dim3 g(fwd_grid_x(a, nunits));
+        if (a.vrows) {
+            if (kmax <= 8) hipLaunchKernelGGL((fwd_planes_kernel<8, true>), g, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fwd_planes_kernel<15, true>), g, dim3(256), 0, st, a);
+        } else {
+            if (kmax <= 8) hipLaunchKernelGGL((fwd_planes_kernel<8, false>), g, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((fwd_planes_kernel<15, false>), g, dim3(256), 0, st, a);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int J = a.plane_stride / 2; // words per plane row
-        const unsigned hb = (unsigned)std::min(nunits, 256);
+        const unsigned hb = (unsigned)std::min(nunits, 256) / 8 * 8 + (nunits < 8 ? (unsigned)nunits : 0u);
         if (J == 1) {
             if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<1, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
             else hipLaunchKernelGGL((planes_hist_kernel<1, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
@@ -2674,17 +2837,23 @@ hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hi
         }
         return hipGetLastError();
     }
-    const dim3 grid((unsigned)nunits, (unsigned)tiles, 1);
+    const dim3 grid(fwd_grid_x(a, nunits), (unsigned)tiles, 1);
     const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
-    if (kmax <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4, false>), grid, dim3(256), lds, st, a);
-    else if (kmax <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2, false>), grid, dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1, false>), grid, dim3(256), lds, st, a);
+    if (a.vrows) {
+        if (kmax <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4, true>), grid, dim3(256), lds, st, a);
+        else if (kmax <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2, true>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1, true>), grid, dim3(256), lds, st, a);
+    } else {
+        if (kmax <= 8) hipLaunchKernelGGL((fwd_hist_lanes_kernel<8, 4, false>), grid, dim3(256), lds, st, a);
+        else if (kmax <= 16) hipLaunchKernelGGL((fwd_hist_lanes_kernel<16, 2, false>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((fwd_hist_lanes_kernel<32, 1, false>), grid, dim3(256), lds, st, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st)
 {
-    const dim3 grid((unsigned)nunits, (unsigned)tiles, 1);
+    const dim3 grid(fwd_grid_x(a, nunits), (unsigned)tiles, 1);
     return a.vrows ? launch_fwd_vr<true>(a, grid, st) : launch_fwd_vr<false>(a, grid, st);
 }
 

@@ -131,6 +131,7 @@ _SIGS = [
     ("tsat_fwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_fwd_dev_noalloc", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_bwd_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
+    ("tsat_bwd_scatter_dev", _i32, [_P, _P, _i32, _f32, _P, _P, _P]),
     ("tsat_binarize_dev", _i32, [_P, _P, _i32, _i32, _P, _P, _P, _P]),
     ("tsat_get_adam_origin", _i32, [_P, _P]),
     ("tsat_set_adam_origin", _i32, [_P, _i64]),
@@ -518,6 +519,10 @@ class Solver:
 
     def bwd_dev(self, bits_ptr: int, n: int, tau: float, dS_ptr: int, U_ptr: int, stream: int | None = None) -> None:
         _check(lib().tsat_bwd_dev(self._h, bits_ptr, int(n), float(tau), dS_ptr, U_ptr, stream))
+
+    def bwd_scatter_dev(self, bits_ptr: int, n: int, tau: float, dS_ptr: int, U_ptr: int,
+                        stream: int | None = None) -> None:
+        _check(lib().tsat_bwd_scatter_dev(self._h, bits_ptr, int(n), float(tau), dS_ptr, U_ptr, stream))
 
     def binarize_dev(self, theta_ptr: int, n: int, mode: int, bits_ptr: int | None, assign_ptr: int | None,
                      mu_ptr: int | None, stream: int | None = None) -> None:

@@ -35,4 +35,6 @@ def test_byte_models():
     assert sb["step_fused_min"] == sb["fwd"] + sb["update"]
     imp = bench.implementation_bytes(cnf, N, True)
     assert imp["planes_write"] == cnf.num_clauses * 2 * 4 * 8
+    mixed = gen.CNF.from_clauses(10, [[1, 2], [3, 4, 5], [1, 2, 3, 4, 5, 6]])
+    assert bench.implementation_bytes(mixed, 64, True)["planes_write"] == (2 + 2 + 4) * 1 * 8
     assert bench.uses_clause_planes(cnf, N, 1) and not bench.uses_clause_planes(cnf, 257, 1)
