@@ -113,13 +113,14 @@ def frac_entry(nbytes, ms, kernel=None):
 
 KERNEL_SOURCES = ["paper_2511_07737_amd/csrc/tsat_kernels.hip", "paper_2511_07737_amd/csrc/tsat_device.h"]
 PROFILE_FILES = {"large": "profiles/var_window_kernel__planted-3sat_V1e6_C4.1e6_N256.txt",
-                 "structured": "profiles/var_kernel__structured_V5e5_C2.5e6_N128.txt"}
+                 "structured": "profiles/var_window_levels_kernel__structured_V5e5_C2.5e6_N128.txt"}
 
 
 def measured_traffic(workload):
-    """HBM-side bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy
-    kernel), or None when there is none or the kernel sources changed since."""
+    """Bytes per launch of the dominant kernel between L2 and the memory
+    fabric, from the committed rocprofv3 counter summary (read and write
+    requests times their sizes, the sizes read off a copy kernel of known
+    bytes), or None when there is none or the kernel sources changed since."""
     import hashlib
 
     path = PROFILE_FILES.get(workload)
