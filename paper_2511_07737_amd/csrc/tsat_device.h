@@ -106,6 +106,11 @@ struct SminArgs {
     double tau, lr0, decay, lr_min, beta1, beta2, weight_decay, conv_frac;
 };
 
+// Levels counted by the mixed-width window gather for a widest clause of K
+// literals (one kernel instance per value); its dL/dR table in LDS has
+// levels + 1 rows, the rows beyond K zero.
+inline int levels_for_width(int K) { return K <= 3 ? 3 : (K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 12 ? 12 : 15))); }
+
 struct VarArgs {
     int32_t V, N, W, Np, K1, mode;
     int32_t lit_rows;         // 1: V rows of logits, each one literal's own row of

@@ -236,11 +236,13 @@ static int32_t row_words(int32_t W) { return W <= 2 ? W : (W <= 4 ? 4 : (W <= 8 
 static bool uniform_plane_store(const tsat_solver* s) { return s->st.pure_k == 2 || s->st.pure_k == 3; }
 
 // LDS of the mixed-width window gather: four windows of P J 64 words and one
-// dL/dR table of K1 J 64 floats per block (one instance) or per wave (batch)
+// dL/dR table of (levels + 1) J 64 floats per block (one instance) or per
+// wave (batch)
 static size_t levels_lds_bytes(const tsat_solver* s, int32_t J)
 {
     const size_t P = (size_t)planes_for_width(s->st.K);
-    return 4 * P * J * 64 * 8 + (s->st.n_inst > 1 ? 4 : 1) * (size_t)K1_of(s) * J * 64 * 4;
+    const size_t rows = (size_t)levels_for_width(s->st.K) + 1;
+    return 4 * P * J * 64 * 8 + (s->st.n_inst > 1 ? 4 : 1) * rows * J * 64 * 4;
 }
 
 // The clause-plane update applies: clause-index records exist (widths up to

@@ -1595,36 +1595,99 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8))) voi
 // var_plane_kernel, so the results are identical.
 // ---------------------------------------------------------------------------
 
-// 64 x 64 bit-matrix transpose across the wave: lane i holds row i (bit c is
-// element (i, c)); afterwards lane c holds column c (bit i is element (i, c)).
-// Stage b (32, 16, ..., 1) exchanges the off-diagonal b x b blocks of lanes i
-// and i ^ b: the lane with bit b clear keeps the columns with bit b clear and
-// takes its partner's, shifted up by b; the other keeps the columns with bit
-// b set and takes its partner's, shifted down.  Below b = 32 the blocks lie
-// inside 32-bit halves, so the shift is a rotation whose wrapped bits fall
-// under the kept mask.
-__device__ __forceinline__ uint64_t transpose64(uint64_t x, uint32_t lane)
+// 64 x 64 bit-matrix transposes across the wave, E matrices at once: lane i
+// holds row i of each (bit c is element (i, c)); afterwards lane c holds
+// column c (bit i is element (i, c)).  A transpose exchanges lane-index bit
+// k with column-index bit k for k = 5 .. 0, all on the VALU (no LDS round
+// trips), every stage applied to the E words before the next:
+//  - bit 5 (the 32-bit half of the word): v_permlane32_swap trades the upper
+//    lanes' low dwords for the lower lanes' high dwords, which is exactly
+//    that exchange;
+//  - bit 4: v_permlane16_swap makes the same trade between odd and even
+//    16-lane rows, so the 16-bit halves are first moved so that column bit 4
+//    selects the dword (one byte permute per dword), swapped, and moved back;
+//  - bit 3 (a byte within a 16-bit half): the partner lane i ^ 8 is a
+//    rotation of the 16-lane row by 8 (DPP), and one byte permute keeps this
+//    lane's bytes and inserts the partner's;
+//  - bits 2, 1, 0: the partner's dword arrives through DPP (lane i ^ 4 as
+//    two shifts by 4 within the row, each written to half of the banks;
+//    i ^ 2 and i ^ 1 as quad permutations); the lane with bit k clear keeps
+//    its columns with bit k clear and takes the partner's ones rotated up by
+//    2^k, the other keeps the columns with bit k set and takes the partner's
+//    rotated down (the wrapped bits fall under the kept mask).
+template <int E>
+__device__ __forceinline__ void transpose64_n(uint64_t (&x)[E], uint32_t lane)
 {
-    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    {
-        const bool up = lane & 32u;
-        const uint32_t got = (uint32_t)__shfl_xor((int)(up ? lo : hi), 32);
-        if (up) lo = got;
-        else hi = got;
-    }
-    const uint32_t keep_lo[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+    uint32_t lo[E], hi[E];
 #pragma unroll
-    for (int st = 0; st < 5; ++st) {
-        const uint32_t b = 16u >> st;
-        const bool up = lane & b;
-        const uint32_t keep = up ? ~keep_lo[st] : keep_lo[st];
-        const uint32_t rot = up ? b : 32u - b; // rotate right: down by b, or up by b
-        const uint32_t plo = (uint32_t)__shfl_xor((int)lo, (int)b);
-        const uint32_t phi = (uint32_t)__shfl_xor((int)hi, (int)b);
-        lo = (keep & lo) | (~keep & __builtin_amdgcn_alignbit(plo, plo, rot));
-        hi = (keep & hi) | (~keep & __builtin_amdgcn_alignbit(phi, phi, rot));
+    for (int e = 0; e < E; ++e) {
+        lo[e] = (uint32_t)x[e];
+        hi[e] = (uint32_t)(x[e] >> 32);
     }
-    return ((uint64_t)hi << 32) | lo;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const auto r = __builtin_amdgcn_permlane32_swap(lo[e], hi[e], false, false);
+        lo[e] = r[0];
+        hi[e] = r[1];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        // low halves to lo, high halves to hi; swap; and back
+        const uint32_t a = __builtin_amdgcn_perm(hi[e], lo[e], 0x05040100u);
+        const uint32_t b = __builtin_amdgcn_perm(hi[e], lo[e], 0x07060302u);
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        lo[e] = __builtin_amdgcn_perm(r[1], r[0], 0x05040100u);
+        hi[e] = __builtin_amdgcn_perm(r[1], r[0], 0x07060302u);
+    }
+    {
+        // bytes (own 0, partner 0, own 2, partner 2) or (partner 1, own 1, partner 3, own 3)
+        const uint32_t sel = (lane & 8u) ? 0x03070105u : 0x06020400u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t tl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[e], 0x128, 0xF, 0xF, false);
+            const uint32_t th = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[e], 0x128, 0xF, 0xF, false);
+            lo[e] = __builtin_amdgcn_perm(tl, lo[e], sel);
+            hi[e] = __builtin_amdgcn_perm(th, hi[e], sel);
+        }
+    }
+    {
+        const bool up = lane & 4u;
+        const uint32_t keep = up ? 0xF0F0F0F0u : 0x0F0F0F0Fu, rot = up ? 4u : 28u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            // banks 0 and 2 of a row read lane i + 4, banks 1 and 3 lane i - 4
+            uint32_t tl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[e], 0x104, 0xF, 0x5, false);
+            tl = (uint32_t)__builtin_amdgcn_update_dpp((int)tl, (int)lo[e], 0x114, 0xF, 0xA, false);
+            uint32_t th = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[e], 0x104, 0xF, 0x5, false);
+            th = (uint32_t)__builtin_amdgcn_update_dpp((int)th, (int)hi[e], 0x114, 0xF, 0xA, false);
+            lo[e] = (keep & lo[e]) | (~keep & __builtin_amdgcn_alignbit(tl, tl, rot));
+            hi[e] = (keep & hi[e]) | (~keep & __builtin_amdgcn_alignbit(th, th, rot));
+        }
+    }
+    {
+        const bool up = lane & 2u;
+        const uint32_t keep = up ? 0xCCCCCCCCu : 0x33333333u, rot = up ? 2u : 30u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t tl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[e], 0x4E, 0xF, 0xF, false); // [2,3,0,1]
+            const uint32_t th = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[e], 0x4E, 0xF, 0xF, false);
+            lo[e] = (keep & lo[e]) | (~keep & __builtin_amdgcn_alignbit(tl, tl, rot));
+            hi[e] = (keep & hi[e]) | (~keep & __builtin_amdgcn_alignbit(th, th, rot));
+        }
+    }
+    {
+        const bool up = lane & 1u;
+        const uint32_t keep = up ? 0xAAAAAAAAu : 0x55555555u, rot = up ? 1u : 31u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t tl = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo[e], 0xB1, 0xF, 0xF, false); // [1,0,3,2]
+            const uint32_t th = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi[e], 0xB1, 0xF, 0xF, false);
+            lo[e] = (keep & lo[e]) | (~keep & __builtin_amdgcn_alignbit(tl, tl, rot));
+            hi[e] = (keep & hi[e]) | (~keep & __builtin_amdgcn_alignbit(th, th, rot));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = ((uint64_t)hi[e] << 32) | lo[e];
 }
 
 // Planes of records [w, w + 64) (records at or past `end` read as zero),
@@ -1646,10 +1709,9 @@ __device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32
         wd[2 * k] = ((uint64_t)q.y << 32) | q.x;
         wd[2 * k + 1] = ((uint64_t)q.w << 32) | q.z;
     }
+    transpose64_n<2 * J>(wd, lane);
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int j = 0; j < J; ++j) win[(p * J + j) * 64 + lane] = transpose64(wd[p * J + j], lane);
+    for (int e = 0; e < 2 * J; ++e) win[e * 64 + lane] = wd[e];
 }
 
 // bits [lo, hi) of a 64-bit word, 0 <= lo < hi <= 64
@@ -2042,8 +2104,9 @@ __device__ __forceinline__ void load_window_p(const VarArgs& a, uint32_t w, uint
         wd[2 * k] = ((uint64_t)q.y << 32) | q.x;
         wd[2 * k + 1] = ((uint64_t)q.w << 32) | q.z;
     }
+    transpose64_n<P * J>(wd, lane);
 #pragma unroll
-    for (int e = 0; e < P * J; ++e) win[e * 64 + lane] = transpose64(wd[e], lane);
+    for (int e = 0; e < P * J; ++e) win[e * 64 + lane] = wd[e];
 }
 
 template <int J, int KT, int OP>
@@ -2065,17 +2128,19 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
     const int W = a.W, K1 = a.K1, Np = a.Np;
     const StepScalars c = load_scalars(a, OP);
     // dynamic LDS: [4][P J 64] u64 windows, then the dL/dR table(s)
-    // [K1][J][64] f32, one per block (single instance) or one per wave
+    // [KT + 1][J][64] f32 (rows at and past K1 zero), one per block (single
+    // instance) or one per wave
+    constexpr int KR = KT + 1;
     extern __shared__ uint64_t lds_lv[];
     uint64_t* my_win = lds_lv + (size_t)wv * (P * J * 64);
     float* gt_base = (float*)(lds_lv + 4 * P * J * 64);
     const bool per_wave = a.var_inst != nullptr;
-    float* my_gt = gt_base + (per_wave ? (size_t)wv * K1 * J * 64 : 0);
+    float* my_gt = gt_base + (per_wave ? (size_t)wv * KR * J * 64 : 0);
     uint32_t gt_inst = 0xffffffffu;
     if (!per_wave) {
-        for (int e = threadIdx.x; e < K1 * J * 64; e += 256) {
+        for (int e = threadIdx.x; e < KR * J * 64; e += 256) {
             const int r = e / (J * 64), j = (e / 64) % J, l = e % 64;
-            my_gt[e] = (j < W) ? a.tbl[(size_t)r * Np + 64 * j + l] : 0.f;
+            my_gt[e] = (r < K1 && j < W) ? a.tbl[(size_t)r * Np + 64 * j + l] : 0.f;
         }
         __syncthreads();
         gt_inst = 0;
@@ -2098,9 +2163,11 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
             if (vi.inst != gt_inst) { // per-wave tables only
                 gt_inst = vi.inst;
                 const float* tg = a.tbl + (size_t)vi.inst * K1 * Np;
-                for (int r = 0; r < K1; ++r)
 #pragma unroll
-                    for (int j = 0; j < J; ++j) my_gt[(r * J + j) * 64 + lane] = (j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
+                for (int r = 0; r < KR; ++r)
+#pragma unroll
+                    for (int j = 0; j < J; ++j)
+                        my_gt[(r * J + j) * 64 + lane] = (r < K1 && j < W) ? tg[(size_t)r * Np + 64 * j + lane] : 0.f;
             }
             const uint32_t r0 = sload(a.cid_off + v), rm = sload(a.cid_mid + v), r1 = sload(a.cid_off + v + 1);
             // per level r and word j: (positive - negative records with
@@ -2140,8 +2207,10 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
             // U = sum over r of (positive - negative records with R = r)
             // dL/dR[r]: with D_r = cnt[r - 1] - dn (positive - negative
             // records with R >= r), that difference is D_r - D_(r+1), i.e.
-            // dp - cnt[0] at r = 0, cnt[r - 1] - cnt[r] inside and cnt[K - 1] - dn
-            // at the widest clause width K (levels above K count nothing)
+            // dp - cnt[0] at r = 0, cnt[r - 1] - cnt[r] inside and cnt[KT - 1] - dn
+            // at r = KT.  Levels above the widest clause width K count nothing
+            // (their differences are 0) and meet zero table rows, so every
+            // one of the KT + 1 terms can be formed: u gains exactly +0.
             const int32_t dp = (int32_t)(rm - r0), dn = (int32_t)(r1 - rm);
             double U[J];
 #pragma unroll
@@ -2149,9 +2218,8 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
                 float u = 0.f;
 #pragma unroll
                 for (int r = 0; r <= KT; ++r) {
-                    if (r >= K1) break; // no clause is wider than the store's widest
                     const int32_t hi = r == 0 ? dp + dn : (int32_t)cnt[j][r - 1];
-                    const int32_t lo = (r < KT && r + 1 < K1) ? (int32_t)cnt[j][r] : dn;
+                    const int32_t lo = r < KT ? (int32_t)cnt[j][r] : dn;
                     u = fmaf((float)(hi - lo - (r == 0 ? dn : 0)), my_gt[(r * J + j) * 64 + lane], u);
                 }
                 U[j] = (double)u;
@@ -2289,11 +2357,12 @@ __global__ __launch_bounds__(256) void planes_hist_kernel(FwdArgs a, int nunits)
                 wd[2 * q + 1] = ((uint64_t)v.w << 32) | v.z;
             }
             const uint32_t n = (uint32_t)((u.c1 - c) < 64 ? (u.c1 - c) : 64);
+            transpose64_n<P * J>(wd, lane);
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 uint64_t pw[P];
 #pragma unroll
-                for (int p = 0; p < P; ++p) pw[p] = transpose64(wd[p * J + j], lane);
+                for (int p = 0; p < P; ++p) pw[p] = wd[p * J + j];
                 uint64_t ge[KT];
                 thermometer<P, KT>(pw, ge);
                 cnt[j][0] += n;
@@ -3060,16 +3129,12 @@ static hipError_t launch_plane_j(const VarArgs& a, int op, int blocks, hipStream
 }
 
 // mixed-width window gather: levels KT >= the widest clause (K1 - 1)
-static int levels_of(const VarArgs& a)
-{
-    const int K = a.K1 - 1;
-    return K <= 3 ? 3 : (K <= 4 ? 4 : (K <= 8 ? 8 : (K <= 12 ? 12 : 15)));
-}
+static int levels_of(const VarArgs& a) { return levels_for_width(a.K1 - 1); }
 
 static size_t levels_lds(const VarArgs& a, int J, int KT)
 {
     const size_t P = KT <= 3 ? 2 : 4;
-    return 4 * P * J * 64 * 8 + (a.var_inst ? 4 : 1) * (size_t)a.K1 * J * 64 * 4;
+    return 4 * P * J * 64 * 8 + (a.var_inst ? 4 : 1) * (size_t)(KT + 1) * J * 64 * 4;
 }
 
 template <int J, int KT>
