@@ -193,21 +193,49 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
         for (int r = 0; r < KW; ++r)
 #pragma unroll
             for (int b = 0; b < B; ++b) pl[r][b] = 0;
-        uint32_t n = 0;
+        // this thread's clauses: c0 + it S for it < nit
         const int64_t c0 = u.c0 + slot;
-        for (int it = 0; it < a.CPT; ++it) {
+        const int64_t rem = u.c1 - c0;
+        const int nit = rem <= 0 ? 0 : (int)(rem < (int64_t)a.CPT * S ? (rem + S - 1) / S : a.CPT);
+        const uint32_t n = (uint32_t)nit;
+        // software pipeline over the clauses: while clause it is counted, the
+        // literal dwords of clause it + 1 and the literal codes of clause
+        // it + 2 are in flight (one memory round trip per clause, not two)
+        uint32_t code_nx[KW], x_nx[KW];
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            code_nx[q] = 0u;
+            x_nx[q] = 0u;
+        }
+        if (nit > 0) {
+#pragma unroll
+            for (int q = 0; q < KW; ++q) x_nx[q] = lit_dword<VR>(a.bits32, a.codes[c0 * KW + q], a.W2, d);
+        }
+        if (nit > 1) {
+#pragma unroll
+            for (int q = 0; q < KW; ++q) code_nx[q] = a.codes[(c0 + S) * KW + q];
+        }
+        for (int it = 0; it < nit; ++it) {
             const int64_t c = c0 + (int64_t)it * S;
-            if (c >= u.c1) break;
+            uint32_t x[KW];
+#pragma unroll
+            for (int q = 0; q < KW; ++q) x[q] = x_nx[q];
+            if (it + 1 < nit) {
+#pragma unroll
+                for (int q = 0; q < KW; ++q) x_nx[q] = lit_dword<VR>(a.bits32, code_nx[q], a.W2, d);
+            }
+            if (it + 2 < nit) {
+#pragma unroll
+                for (int q = 0; q < KW; ++q) code_nx[q] = a.codes[(c + 2 * S) * KW + q];
+            }
             uint32_t ge[KW];
 #pragma unroll
             for (int r = 0; r < KW; ++r) ge[r] = 0;
 #pragma unroll
             for (int q = 0; q < KW; ++q) {
-                const uint32_t code = a.codes[c * KW + q];
-                const uint32_t x = lit_dword<VR>(a.bits32, code, a.W2, d);
 #pragma unroll
-                for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x;
-                ge[0] |= x;
+                for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x[q];
+                ge[0] |= x[q];
             }
             if (a.planes) {
                 // R in binary for the backward, plane_P planes: bit p of R is
@@ -232,7 +260,6 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
                     carry = t;
                 }
             }
-            ++n;
         }
         if (n) {
             for (int p = 0; p < 32; ++p) {
