@@ -83,6 +83,10 @@ struct FwdArgs {
     // launch; a unit's width is in its pad field
     const uint32_t* wide_codes[TSAT_MAX_WIDTH + 1];
     int64_t wide_base[TSAT_MAX_WIDTH + 1];
+    // all buckets in one launch (fwd_multi_kernel): codes and plane base of
+    // every width in wide_codes / wide_base; the four-plane region (widths
+    // 4 and up) starts wide_off dwords after planes
+    int64_t wide_off;
 };
 
 struct SminArgs {
@@ -177,6 +181,8 @@ struct SelectArgs {
 
 hipError_t launch_fwd(const FwdArgs& a, int nunits, int tiles, hipStream_t st);
 hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st);
+hipError_t launch_fwd_multi(const FwdArgs& a, int kmax, int nunits, hipStream_t st);
+hipError_t launch_planes_hist(const FwdArgs& a, int kmax, int nunits, hipStream_t st);
 hipError_t launch_smin(const SminArgs& a, hipStream_t st);
 hipError_t launch_adj_scatter(const uint32_t* codes, int64_t Cb, int k, int N, int K1, const uint32_t* bits32,
                               int W2, const float* tbl, float* U, int V, hipStream_t st);

@@ -95,6 +95,9 @@ struct tsat_solver {
 
     // forward work units of all wide buckets (widths > 4) in one launch, per clauses-per-wave
     std::map<int, std::pair<DBuf*, int>> wide_units;
+    // forward work units of every bucket in one launch (mixed widths with
+    // clause planes), per clauses-per-thread
+    std::map<int, std::pair<DBuf*, int>> multi_units;
 
     // learned proposal: features and aggregation channels, kept proposal
     DBuf feat, fh[2], fzinv, prop;
@@ -117,6 +120,7 @@ struct tsat_solver {
         drop_graph();
         for (auto* b : buckets) delete b;
         for (auto& u : wide_units) delete u.second.first;
+        for (auto& u : multi_units) delete u.second.first;
         for (auto e : events) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -209,9 +213,19 @@ static int32_t bucket_units(tsat_solver* s, Bucket* b, const FwdGeom& g, const F
 // capture, which must not allocate or copy).
 static int32_t wide_geometry(const tsat_solver* s, int32_t N, FwdGeom* g, int* kmax);
 static int32_t wide_units(tsat_solver* s, const FwdGeom& g, const FwdUnit** out, int* count);
+static bool multi_path(const tsat_solver* s, int32_t N);
+static FwdGeom multi_geometry(const tsat_solver* s, int32_t N, int* kmax);
+static int32_t multi_units(tsat_solver* s, const FwdGeom& g, const FwdUnit** out, int* count);
 
 static int32_t prepare_units(tsat_solver* s, int32_t N)
 {
+    if (multi_path(s, N)) {
+        int kmax;
+        const FwdGeom g = multi_geometry(s, N, &kmax);
+        const FwdUnit* u;
+        int n;
+        RET(multi_units(s, g, &u, &n));
+    }
     for (auto* b : s->buckets) {
         if (b->count == 0 || b->k == 0 || b->k > 4) continue;
         const FwdGeom g = fwd_geometry(N, K1_of(s), b->count, b->k, s->fwd_target_blocks);
@@ -319,6 +333,58 @@ static int32_t wide_units(tsat_solver* s, const FwdGeom& g, const FwdUnit** out,
     return TSAT_OK;
 }
 
+// Every bucket of a store with two or more non-empty widths in one forward
+// launch: clause planes on (so at most 256 candidates, one tile per block).
+static bool multi_path(const tsat_solver* s, int32_t N)
+{
+    if (!plane_path(s, N)) return false;
+    int nb = 0;
+    for (auto* b : s->buckets)
+        if (b->k > 0 && b->count > 0) ++nb;
+    return nb >= 2;
+}
+
+static FwdGeom multi_geometry(const tsat_solver* s, int32_t N, int* kmax)
+{
+    int64_t C = 0;
+    *kmax = 0;
+    for (auto* b : s->buckets)
+        if (b->k > 0 && b->count > 0) {
+            C += b->count;
+            *kmax = std::max(*kmax, b->k);
+        }
+    return fwd_geometry(N, K1_of(s), C, 4, s->fwd_target_blocks);
+}
+
+// per bucket (width in pad) and instance, ranges of S CPT clauses
+static int32_t multi_units(tsat_solver* s, const FwdGeom& g, const FwdUnit** out, int* count)
+{
+    auto it = s->multi_units.find(g.CPT);
+    if (it == s->multi_units.end()) {
+        std::vector<FwdUnit> u;
+        const int64_t per = (int64_t)g.S * g.CPT;
+        for (auto* b : s->buckets) {
+            if (b->k == 0 || b->count == 0) continue;
+            const auto& off = s->st.inst_off[b->k];
+            for (int32_t j = 0; j < s->st.n_inst; ++j)
+                for (int64_t c = off[j]; c < off[j + 1]; c += per)
+                    u.push_back(FwdUnit{j, b->k, c, std::min(c + per, off[j + 1])});
+        }
+        DBuf* d = new (std::nothrow) DBuf();
+        if (!d) return fail(TSAT_E_OOM, "host allocation failed");
+        int32_t rc = d->alloc(std::max<size_t>(1, u.size()) * sizeof(FwdUnit), "forward units");
+        if (rc) { delete d; return rc; }
+        if (!u.empty()) {
+            hipError_t e = hipMemcpy(d->p, u.data(), u.size() * sizeof(FwdUnit), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { delete d; return fail(TSAT_E_HIP, "unit upload: %s", hipGetErrorString(e)); }
+        }
+        it = s->multi_units.emplace(g.CPT, std::make_pair(d, (int)u.size())).first;
+    }
+    *out = it->second.first->as<FwdUnit>();
+    *count = it->second.second;
+    return TSAT_OK;
+}
+
 static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint32_t* H, const Ctrl* ctrl,
                            const InstCtrl* ictrl, hipStream_t st, uint32_t* planes = nullptr)
 {
@@ -340,6 +406,41 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
         base.planes = planes;
         base.plane_stride = 2 * row_words(W);
         wide_planes = planes + (size_t)G3 * 2 * base.plane_stride;
+    }
+    if (with_planes && multi_path(s, N)) {
+        // every bucket in one launch, then the wide clauses' histogram pass
+        int kmax = 0;
+        const FwdGeom g = multi_geometry(s, N, &kmax);
+        FwdArgs a = base;
+        int nunits = 0;
+        RET(multi_units(s, g, &a.units, &nunits));
+        a.KW = 0;
+        a.Dn = g.Dn;
+        a.DT = g.DT;
+        a.CPT = g.CPT;
+        a.plane_P = 2;
+        a.wide_off = (int64_t)G3 * 2 * base.plane_stride;
+        for (auto* b : s->buckets) {
+            if (b->k == 0 || b->count == 0) continue;
+            a.wide_codes[b->k] = b->codes.as<uint32_t>();
+            a.wide_base[b->k] = s->st.plane_base[b->k] - (b->k <= 3 ? 0 : G3);
+        }
+        a.nunits = nunits;
+        a.xcd = s->xcd_order;
+        if (nunits > 0) HIPCHK(launch_fwd_multi(a, kmax, nunits, st));
+        FwdGeom gw;
+        int kw = 0;
+        if (wide_geometry(s, N, &gw, &kw)) {
+            FwdArgs w = a;
+            int nw = 0;
+            RET(wide_units(s, gw, &w.units, &nw));
+            w.CPT = gw.CPT;
+            w.planes = wide_planes;
+            w.plane_P = 4;
+            w.nunits = nw;
+            if (nw > 0) HIPCHK(launch_planes_hist(w, kw, nw, st));
+        }
+        return TSAT_OK;
     }
     // widths 1 .. 4: one launch per bucket
     for (auto* b : s->buckets) {
@@ -675,6 +776,8 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     s->buckets.clear();
     for (auto& u : s->wide_units) delete u.second.first;
     s->wide_units.clear();
+    for (auto& u : s->multi_units) delete u.second.first;
+    s->multi_units.clear();
     s->loaded = false;
     s->lit_rows_req = 0;
     s->rows_per_var = 1;

@@ -170,15 +170,14 @@ __device__ __forceinline__ uint32_t lit_dword(const uint32_t* __restrict__ bits3
     return bits32[(size_t)code * W2 + d];
 }
 
+// One work unit of a width-KW bucket: the block's clauses [u.c0, u.c1),
+// their literal codes in `codes` (KW per clause), planes of R written to
+// `planes` ([clause][plane_P][plane_stride] dwords from clause plane_base)
+// when non-null.  lh: the block's LDS bins, [DT*32][KW+1].
 template <int KW, int B, bool VR>
-__global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
+__device__ __forceinline__ void fwd_hist_unit(const FwdArgs& a, const FwdUnit& u, const uint32_t* __restrict__ codes,
+                                              uint32_t* planes, int plane_P, int64_t plane_base, uint32_t* lh)
 {
-    extern __shared__ uint32_t lh[]; // [DT*32][KW+1]
-    if (a.ctrl && a.ctrl->stop) return;
-    const uint32_t un = xcd_unit(a.xcd, (uint32_t)a.nunits);
-    if (un >= (uint32_t)a.nunits) return;
-    const FwdUnit u = a.units[un];
-    if (a.ictrl && a.ictrl[u.inst].frozen) return;
     uint32_t* H = a.H + (size_t)u.inst * a.H_stride;
     const int tid = threadIdx.x;
     const int DT = a.DT;
@@ -209,11 +208,11 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
         }
         if (nit > 0) {
 #pragma unroll
-            for (int q = 0; q < KW; ++q) x_nx[q] = lit_dword<VR>(a.bits32, a.codes[c0 * KW + q], a.W2, d);
+            for (int q = 0; q < KW; ++q) x_nx[q] = lit_dword<VR>(a.bits32, codes[c0 * KW + q], a.W2, d);
         }
         if (nit > 1) {
 #pragma unroll
-            for (int q = 0; q < KW; ++q) code_nx[q] = a.codes[(c0 + S) * KW + q];
+            for (int q = 0; q < KW; ++q) code_nx[q] = codes[(c0 + S) * KW + q];
         }
         for (int it = 0; it < nit; ++it) {
             const int64_t c = c0 + (int64_t)it * S;
@@ -226,7 +225,7 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
             }
             if (it + 2 < nit) {
 #pragma unroll
-                for (int q = 0; q < KW; ++q) code_nx[q] = a.codes[(c + 2 * S) * KW + q];
+                for (int q = 0; q < KW; ++q) code_nx[q] = codes[(c + 2 * S) * KW + q];
             }
             uint32_t ge[KW];
 #pragma unroll
@@ -237,13 +236,13 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
                 for (int r = KW - 1; r >= 1; --r) ge[r] |= ge[r - 1] & x[q];
                 ge[0] |= x[q];
             }
-            if (a.planes) {
+            if (planes) {
                 // R in binary for the backward, plane_P planes: bit p of R is
                 // the parity of the masks [R >= m 2^p], m >= 1
-                uint32_t* P = a.planes + (size_t)(a.plane_base + c) * (size_t)(a.plane_P * a.plane_stride) + d;
+                uint32_t* P = planes + (size_t)(plane_base + c) * (size_t)(plane_P * a.plane_stride) + d;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    if (p >= a.plane_P) break;
+                    if (p >= plane_P) break;
                     uint32_t bp = 0;
 #pragma unroll
                     for (int r = 1 << p; r <= KW; r += 1 << p) bp ^= ge[r - 1];
@@ -288,6 +287,18 @@ __global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
         const int dd = blockIdx.y * DT + cl / 32;
         if (dd < a.Dn) atomicAdd(&H[(size_t)(blockIdx.y * DT * 32 + cl) * a.K1 + r], val);
     }
+}
+
+template <int KW, int B, bool VR>
+__global__ __launch_bounds__(256) void fwd_hist_kernel(FwdArgs a)
+{
+    extern __shared__ uint32_t lh[]; // [DT*32][KW+1]
+    if (a.ctrl && a.ctrl->stop) return;
+    const uint32_t un = xcd_unit(a.xcd, (uint32_t)a.nunits);
+    if (un >= (uint32_t)a.nunits) return;
+    const FwdUnit u = a.units[un];
+    if (a.ictrl && a.ictrl[u.inst].frozen) return;
+    fwd_hist_unit<KW, B, VR>(a, u, a.codes, a.planes, a.plane_P, a.plane_base, lh);
 }
 
 // Wide clauses (k > 4): one lane per candidate.  A wave takes a run of
@@ -2276,6 +2287,70 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
 // the global histogram (integer atomics, so the result is exact).
 // ---------------------------------------------------------------------------
 
+// One work unit of wide clauses (width k <= KMAX): the planes of R of its
+// clauses, pipelined like fwd_hist_unit (the literal dwords of the next
+// clause and the codes of the one after in flight while a clause is added).
+template <int KMAX, bool VR>
+__device__ __forceinline__ void fwd_planes_unit(const FwdArgs& a, const FwdUnit& u, int k,
+                                                const uint32_t* __restrict__ codes, uint32_t* planes, int64_t base)
+{
+    const int Dn = a.Dn, S = 256 / Dn;
+    const int slot = threadIdx.x / Dn, d = threadIdx.x % Dn;
+    if (slot >= S) return;
+    const size_t prow = (size_t)4 * a.plane_stride; // dwords of one clause's planes
+    const int64_t c0 = u.c0 + slot;
+    const int64_t rem = u.c1 - c0;
+    const int nit = rem <= 0 ? 0 : (int)((rem + S - 1) / S);
+    uint32_t code_nx[KMAX], x_nx[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        code_nx[q] = 0u;
+        x_nx[q] = 0u;
+    }
+    if (nit > 0) {
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+            if (q < k) x_nx[q] = lit_dword<VR>(a.bits32, codes[c0 * k + q], a.W2, d);
+    }
+    if (nit > 1) {
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+            if (q < k) code_nx[q] = codes[(c0 + S) * k + q];
+    }
+    for (int it = 0; it < nit; ++it) {
+        const int64_t c = c0 + (int64_t)it * S;
+        uint32_t x[KMAX];
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) x[q] = x_nx[q];
+        if (it + 1 < nit) {
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q)
+                if (q < k) x_nx[q] = lit_dword<VR>(a.bits32, code_nx[q], a.W2, d);
+        }
+        if (it + 2 < nit) {
+#pragma unroll
+            for (int q = 0; q < KMAX; ++q)
+                if (q < k) code_nx[q] = codes[(c + 2 * S) * k + q];
+        }
+        uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0; // R < 16: a 4-bit counter per candidate
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            const uint32_t c0b = r0 & x[q];
+            r0 ^= x[q];
+            const uint32_t c1b = r1 & c0b;
+            r1 ^= c0b;
+            const uint32_t c2b = r2 & c1b;
+            r2 ^= c1b;
+            r3 ^= c2b;
+        }
+        uint32_t* P = planes + (size_t)(base + c) * prow + d;
+        P[0] = r0;
+        P[(size_t)a.plane_stride] = r1;
+        P[(size_t)2 * a.plane_stride] = r2;
+        P[(size_t)3 * a.plane_stride] = r3;
+    }
+}
+
 template <int KMAX, bool VR>
 __global__ __launch_bounds__(256) void fwd_planes_kernel(FwdArgs a)
 {
@@ -2285,34 +2360,35 @@ __global__ __launch_bounds__(256) void fwd_planes_kernel(FwdArgs a)
     const FwdUnit u = a.units[un];
     if (a.ictrl && a.ictrl[u.inst].frozen) return;
     const int k = u.pad;
+    fwd_planes_unit<KMAX, VR>(a, u, k, a.wide_codes[k], a.planes, a.wide_base[k]);
+}
+
+// Every bucket of a mixed-width store in one launch (clause planes on, at
+// most 256 candidates, so a block's tile is all of them): a unit of width
+// k <= 4 is a histogram unit of fwd_hist_unit (widths up to 3 write two
+// planes from the start of the plane buffer, width 4 four planes in the
+// wide region), a wider one a planes unit of fwd_planes_unit; the histogram
+// of the wide clauses then comes from planes_hist_kernel.  Small buckets no
+// longer run as launches of their own with too few waves to hide latency.
+template <int KMAX, bool VR>
+__global__ __launch_bounds__(256) void fwd_multi_kernel(FwdArgs a)
+{
+    extern __shared__ uint32_t lh[]; // [DT*32][5]
+    if (a.ctrl && a.ctrl->stop) return;
+    const uint32_t un = xcd_unit(a.xcd, (uint32_t)a.nunits);
+    if (un >= (uint32_t)a.nunits) return;
+    const FwdUnit u = a.units[un];
+    if (a.ictrl && a.ictrl[u.inst].frozen) return;
+    const int k = u.pad; // block-uniform
     const uint32_t* codes = a.wide_codes[k];
     const int64_t base = a.wide_base[k];
-    const int Dn = a.Dn, S = 256 / Dn;
-    const int slot = threadIdx.x / Dn, d = threadIdx.x % Dn;
-    if (slot >= S) return;
-    const size_t prow = (size_t)a.plane_P * a.plane_stride; // dwords of one clause's planes
-    for (int64_t c = u.c0 + slot; c < u.c1; c += S) {
-        uint32_t code[KMAX], x[KMAX];
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) code[q] = q < k ? codes[c * k + q] : 0u;
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) x[q] = q < k ? lit_dword<VR>(a.bits32, code[q], a.W2, d) : 0u;
-        uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0; // R < 16
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-            const uint32_t c0 = r0 & x[q];
-            r0 ^= x[q];
-            const uint32_t c1 = r1 & c0;
-            r1 ^= c0;
-            const uint32_t c2 = r2 & c1;
-            r2 ^= c1;
-            r3 ^= c2;
-        }
-        uint32_t* P = a.planes + (size_t)(base + c) * prow + d;
-        P[0] = r0;
-        P[(size_t)a.plane_stride] = r1;
-        P[(size_t)2 * a.plane_stride] = r2;
-        P[(size_t)3 * a.plane_stride] = r3;
+    uint32_t* planes4 = a.planes + a.wide_off;
+    switch (k) {
+    case 1: fwd_hist_unit<1, 8, VR>(a, u, codes, a.planes, 2, base, lh); break;
+    case 2: fwd_hist_unit<2, 8, VR>(a, u, codes, a.planes, 2, base, lh); break;
+    case 3: fwd_hist_unit<3, 8, VR>(a, u, codes, a.planes, 2, base, lh); break;
+    case 4: fwd_hist_unit<4, 8, VR>(a, u, codes, planes4, 4, base, lh); break;
+    default: fwd_planes_unit<KMAX, VR>(a, u, k, codes, planes4, base); break;
     }
 }
 
@@ -2906,6 +2982,41 @@ static unsigned fwd_grid_x(const FwdArgs& a, int nunits)
 // every wide bucket (widths 5 .. kmax) in one launch: a.KW = 0, unit widths in
 // pad.  With clause planes (four per clause, kmax <= 15): the planes pass,
 // then the histogram pass over the planes; else the lane-per-candidate kernel.
+// the histogram pass over the wide clauses' planes (units of the wide
+// buckets, a.planes at the four-plane region)
+hipError_t launch_planes_hist(const FwdArgs& a, int kmax, int nunits, hipStream_t st)
+{
+    const int J = a.plane_stride / 2; // words per plane row
+    const unsigned hb = (unsigned)std::min(nunits, 256) / 8 * 8 + (nunits < 8 ? (unsigned)nunits : 0u);
+    if (J == 1) {
+        if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<1, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
+        else hipLaunchKernelGGL((planes_hist_kernel<1, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
+    } else if (J == 2) {
+        if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<2, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
+        else hipLaunchKernelGGL((planes_hist_kernel<2, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
+    } else {
+        if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<4, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
+        else hipLaunchKernelGGL((planes_hist_kernel<4, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
+    }
+    return hipGetLastError();
+}
+
+// every bucket in one launch (fwd_multi_kernel): a.units hold the units of
+// all widths, the width in pad; LDS for the widest histogram unit (k = 4)
+hipError_t launch_fwd_multi(const FwdArgs& a, int kmax, int nunits, hipStream_t st)
+{
+    const dim3 g(fwd_grid_x(a, nunits));
+    const size_t lds = (size_t)a.DT * 32 * 5 * sizeof(uint32_t);
+    if (a.vrows) {
+        if (kmax <= 8) hipLaunchKernelGGL((fwd_multi_kernel<8, true>), g, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((fwd_multi_kernel<15, true>), g, dim3(256), lds, st, a);
+    } else {
+        if (kmax <= 8) hipLaunchKernelGGL((fwd_multi_kernel<8, false>), g, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((fwd_multi_kernel<15, false>), g, dim3(256), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hipStream_t st)
 {
     if (a.planes && a.plane_P == 4 && kmax <= 15 && a.Dn <= 8) {
@@ -2919,19 +3030,7 @@ hipError_t launch_fwd_wide(const FwdArgs& a, int kmax, int nunits, int tiles, hi
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int J = a.plane_stride / 2; // words per plane row
-        const unsigned hb = (unsigned)std::min(nunits, 256) / 8 * 8 + (nunits < 8 ? (unsigned)nunits : 0u);
-        if (J == 1) {
-            if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<1, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
-            else hipLaunchKernelGGL((planes_hist_kernel<1, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
-        } else if (J == 2) {
-            if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<2, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
-            else hipLaunchKernelGGL((planes_hist_kernel<2, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
-        } else {
-            if (kmax <= 8) hipLaunchKernelGGL((planes_hist_kernel<4, 8>), dim3(hb), dim3(256), 0, st, a, nunits);
-            else hipLaunchKernelGGL((planes_hist_kernel<4, 15>), dim3(hb), dim3(256), 0, st, a, nunits);
-        }
-        return hipGetLastError();
+        return launch_planes_hist(a, kmax, nunits, st);
     }
     const dim3 grid(fwd_grid_x(a, nunits), (unsigned)tiles, 1);
     const size_t lds = (size_t)4 * 64 * a.K1 * sizeof(uint32_t);
