@@ -2147,7 +2147,7 @@ __device__ __forceinline__ void load_window_p(const VarArgs& a, uint32_t w, uint
     for (int e = 0; e < P * J; ++e) win[e * 64 + lane] = wd[e];
 }
 
-template <int J, int KT, int OP>
+template <int J, int KT, int OP, bool FULL = false>
 __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
 {
     if (OP == OP_STEP && a.ctrl->stop) {
@@ -2235,7 +2235,7 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
             }
             float th[J], mm[J], vv[J];
             bool valid[J];
-            load_row<J, OP, false>(a, v, lane, th, mm, vv, valid);
+            load_row<J, OP, FULL>(a, v, lane, th, mm, vv, valid);
             bool clamped = false;
             const double mu = (OP == OP_ADJ || a.mode != 1) ? 1.0 : clamp_mu(sload(a.mu_cur + v), clamped);
             const uint64_t* ownp = a.lits_cur + (size_t)(a.lit_rows ? v : 2 * v) * W;
@@ -3270,11 +3270,29 @@ static auto levels_kernel_ptr(int op)
                          : (op == OP_GRAD ? var_window_levels_kernel<J, KT, OP_GRAD> : var_window_levels_kernel<J, KT, OP_ADJ>);
 }
 
+// the iteration's update with every lane holding a candidate (N = 64 J):
+// no per-lane candidate checks
+template <int J, int KT>
+static auto levels_kernel_full_ptr()
+{
+    return var_window_levels_kernel<J, KT, OP_STEP, true>;
+}
+
 template <int J>
 static hipError_t launch_levels_j(const VarArgs& a, int op, int blocks, hipStream_t st)
 {
     const int KT = levels_of(a);
     const size_t lds = levels_lds(a, J, KT);
+    if (op == OP_STEP && a.N == 64 * J) {
+        switch (KT) {
+        case 3: hipLaunchKernelGGL((levels_kernel_full_ptr<J, 3>()), dim3(blocks), dim3(256), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((levels_kernel_full_ptr<J, 4>()), dim3(blocks), dim3(256), lds, st, a); break;
+        case 8: hipLaunchKernelGGL((levels_kernel_full_ptr<J, 8>()), dim3(blocks), dim3(256), lds, st, a); break;
+        case 12: hipLaunchKernelGGL((levels_kernel_full_ptr<J, 12>()), dim3(blocks), dim3(256), lds, st, a); break;
+        default: hipLaunchKernelGGL((levels_kernel_full_ptr<J, 15>()), dim3(blocks), dim3(256), lds, st, a); break;
+        }
+        return hipGetLastError();
+    }
     switch (KT) {
     case 3: hipLaunchKernelGGL((levels_kernel_ptr<J, 3>(op)), dim3(blocks), dim3(256), lds, st, a); break;
     case 4: hipLaunchKernelGGL((levels_kernel_ptr<J, 4>(op)), dim3(blocks), dim3(256), lds, st, a); break;
