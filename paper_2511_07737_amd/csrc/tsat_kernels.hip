@@ -1966,14 +1966,27 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
     for (uint32_t ch = cr.first; ch < cr.end; ch += cr.stride) {
         const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
         const uint32_t rend = sload(a.occ_off + ve);
+        // variables of one instance are consecutive: a chunk whose first and
+        // last variables share it takes the instance's state once
+        const uint32_t inst_b = a.var_inst ? sload(a.var_inst + vb) : 0u;
+        const uint32_t inst_e = a.var_inst ? sload(a.var_inst + ve - 1) : 0u;
+        const bool one_inst = inst_b == inst_e;
+        VarInst ci;
+        if (one_inst) ci = instance_state<OP>(a, inst_b);
         uint32_t w = 0;
         bool loaded = false;
         for (uint32_t v0 = vb; v0 < ve; v0 += 2) {
             const uint32_t v1 = v0 + 1;
             const bool has1 = v1 < ve; // wave-uniform
-            const VarInst i0 = var_instance<OP>(a, v0);
-            VarInst i1 = i0;
-            if (has1) i1 = var_instance<OP>(a, v1);
+            VarInst i0, i1;
+            if (one_inst) {
+                i0 = ci;
+                i1 = ci;
+            } else {
+                i0 = var_instance<OP>(a, v0);
+                i1 = i0;
+                if (has1) i1 = var_instance<OP>(a, v1);
+            }
             const bool live0 = !i0.frozen, live1 = has1 && !i1.frozen;
             const uint32_t vl = v0 + h;
             const bool present = h ? has1 : true, live = h ? live1 : live0;
