@@ -2089,16 +2089,16 @@ __global__ __launch_bounds__(256) void var_window_pair_kernel(VarArgs a)
 // below 2^q, the new bit itself at 2^q, and (new bit) AND (lower levels)
 // above.  All are ORs and ANDs of the planes (no constant-true term), so
 // planes masked to a record set give levels masked to that set.
-template <int P, int KT>
-__device__ __forceinline__ void thermometer(const uint64_t (&pl)[P], uint64_t (&ge)[KT])
+template <int P, int KT, typename T = uint64_t>
+__device__ __forceinline__ void thermometer(const T (&pl)[P], T (&ge)[KT])
 {
-    uint64_t lv[15]; // levels 1 .. 2^q - 1 of the lower q bits
+    T lv[15]; // levels 1 .. 2^q - 1 of the lower q bits
     lv[0] = pl[0];
     int n = 1; // 2^q - 1
 #pragma unroll
     for (int q = 1; q < P; ++q) {
-        const uint64_t b = pl[q];
-        uint64_t nx[15];
+        const T b = pl[q];
+        T nx[15];
 #pragma unroll
         for (int r = 1; r <= 15; ++r) {
             if (r > 2 * n + 1) break;
@@ -2112,24 +2112,27 @@ __device__ __forceinline__ void thermometer(const uint64_t (&pl)[P], uint64_t (&
             if (r < n) lv[r] = nx[r];
     }
 #pragma unroll
-    for (int r = 0; r < KT; ++r) ge[r] = r < n ? lv[r] : 0ull;
+    for (int r = 0; r < KT; ++r) ge[r] = r < n ? lv[r] : T(0);
 }
 
 // Signed level counts of one variable in one window: with the records of
 // its positive occurrences in mp and of its negative ones in mn (disjoint),
 // popc(mn ^ (G & (mp | mn))) = popc(G & mp) + |mn| - popc(G & mn), so one
 // popcount per level gives (positive - negative records with R >= r) + |mn|.
-template <int P, int KT>
-__device__ __forceinline__ void count_levels(const uint64_t (&pl)[P], uint64_t mp, uint64_t mn, uint32_t (&cnt)[KT])
+template <int P, int KT, typename T = uint64_t>
+__device__ __forceinline__ void count_levels(const T (&pl)[P], T mp, T mn, uint32_t (&cnt)[KT])
 {
-    const uint64_t m = mp | mn;
-    uint64_t pm[P];
+    const T m = mp | mn;
+    T pm[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) pm[p] = pl[p] & m;
-    uint64_t ge[KT];
-    thermometer<P, KT>(pm, ge);
+    T ge[KT];
+    thermometer<P, KT, T>(pm, ge);
 #pragma unroll
-    for (int r = 0; r < KT; ++r) cnt[r] += (uint32_t)__popcll(mn ^ ge[r]);
+    for (int r = 0; r < KT; ++r) {
+        if constexpr (sizeof(T) == 8) cnt[r] += (uint32_t)__popcll(mn ^ ge[r]);
+        else cnt[r] += (uint32_t)__popc(mn ^ ge[r]);
+    }
 }
 
 // Planes of records [w, w + 64) (records at or past `end` read as zero),
@@ -2237,12 +2240,28 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
                 const uint32_t hi = r1 < w + 64u ? r1 : w + 64u;
                 const uint64_t mp = q < rm ? bit_range(q - w, (hi < rm ? hi : rm) - w) : 0ull;
                 const uint64_t mn = hi > rm ? bit_range((q > rm ? q : rm) - w, hi - w) : 0ull;
+                const uint64_t m = mp | mn;
+                if ((uint32_t)(m >> 32) == 0u || (uint32_t)m == 0u) { // wave-uniform
+                    // the variable's records in this window lie in one 32-bit
+                    // half (most do): count on that half's dwords only
+                    const uint32_t hf = (uint32_t)m == 0u ? 1u : 0u;
+                    const uint32_t* win32 = reinterpret_cast<const uint32_t*>(my_win);
+                    const uint32_t mp32 = (uint32_t)(mp >> (32u * hf)), mn32 = (uint32_t)(mn >> (32u * hf));
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    uint64_t pl[P];
+                    for (int j = 0; j < J; ++j) {
+                        uint32_t pl[P];
 #pragma unroll
-                    for (int p = 0; p < P; ++p) pl[p] = my_win[(p * J + j) * 64 + lane];
-                    count_levels<P, KT>(pl, mp, mn, cnt[j]);
+                        for (int p = 0; p < P; ++p) pl[p] = win32[2 * ((p * J + j) * 64 + lane) + hf];
+                        count_levels<P, KT, uint32_t>(pl, mp32, mn32, cnt[j]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        uint64_t pl[P];
+#pragma unroll
+                        for (int p = 0; p < P; ++p) pl[p] = my_win[(p * J + j) * 64 + lane];
+                        count_levels<P, KT>(pl, mp, mn, cnt[j]);
+                    }
                 }
                 q = hi;
             }
