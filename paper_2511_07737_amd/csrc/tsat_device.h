@@ -156,6 +156,10 @@ struct VarArgs {
     uint32_t narrow_end;      // clauses below this global index hold 2 planes, the rest 4 (after them)
     const uint32_t* cid_off;  // [V+1] record offsets of occ_cid
     const uint32_t* cid_mid;  // [V] first record of negative occurrences
+    const uint32_t* vchunk;   // null, or [n_vchunk + 1] first variables of the mixed-width
+                              // window gather's work items (at most 8 variables and
+                              // 64 records each, or one variable)
+    int32_t n_vchunk;
     // generic stores: variables with many occurrence words are split into
     // chunks of records handled by separate waves; their FP64 partial sums
     // are added in chunk order by one wave per variable, which runs the tail

@@ -53,6 +53,8 @@ struct tsat_solver {
     DBuf occ_off, occ_mid, occ_data, var_inst, info;
     DBuf occ_cid;            // clause-index records (widths up to kMaxPlaneWidth)
     DBuf cid_off, cid_mid;   // their record offsets (stores with generic occurrence records)
+    DBuf vchunk;             // work items of the mixed-width window gather: first variables
+    int32_t n_vchunk = 0;
     DBuf planes, planes_scr; // R of every clause in binary, for the step / for evaluations
     DBuf heavy, hv_var, hv_chunk, ch_var, ch_beg, ch_end; // chunked heavy variables (generic stores)
     DBuf partial, partial_scr; // FP64 partial sums of the chunks, for the step / for evaluations
@@ -555,6 +557,8 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.narrow_end = s->loaded && s->occ_cid.p ? (uint32_t)narrow_end(s) : 0u;
     a.cid_off = s->cid_off.p ? s->cid_off.as<uint32_t>() : a.occ_off;
     a.cid_mid = s->cid_mid.p ? s->cid_mid.as<uint32_t>() : a.occ_mid;
+    a.vchunk = s->vchunk.p ? s->vchunk.as<uint32_t>() : nullptr;
+    a.n_vchunk = s->n_vchunk;
     a.planes = s->planes_scr.as<uint32_t>();
     if (s->heavy.p) {
         a.heavy = s->heavy.as<uint32_t>();
@@ -579,6 +583,7 @@ static void batch_rows(const tsat_solver* s, VarArgs& a)
     a.V = 2 * s->st.V;
     a.lit_rows = 1;
     a.occ_off = a.cid_off = s->lro.as<uint32_t>();
+    a.vchunk = nullptr; // built over the variables' records, not the literals'
     a.occ_mid = a.cid_mid = s->lro.as<uint32_t>() + 1;
     a.var_inst = nullptr;
     a.window = 1;
@@ -823,6 +828,26 @@ static int32_t load_store(tsat_solver* s, Store&& st)
         RET(s->cid_mid.alloc(std::max<size_t>(1, V) * 4, "clause-index record offsets"));
         HIPCHK(hipMemcpy(s->cid_off.p, s->st.cid_off.data(), (V + 1) * 4, hipMemcpyHostToDevice));
         if (V) HIPCHK(hipMemcpy(s->cid_mid.p, s->st.cid_mid.data(), V * 4, hipMemcpyHostToDevice));
+    }
+    // work items of the mixed-width window gather: runs of consecutive
+    // variables whose records fill one 64-record window (at most 8
+    // variables; a variable with more records alone)
+    s->vchunk.release();
+    s->n_vchunk = 0;
+    if (!s->st.cid_off.empty() && V > 0) {
+        const std::vector<uint32_t>& off = s->st.cid_off;
+        std::vector<uint32_t> ch;
+        for (size_t v = 0; v < V;) {
+            size_t e = v;
+            while (e < V && e - v < 8 && off[e + 1] - off[v] <= 64) ++e;
+            if (e == v) e = v + 1;
+            ch.push_back((uint32_t)v);
+            v = e;
+        }
+        ch.push_back((uint32_t)V);
+        RET(s->vchunk.alloc(ch.size() * 4, "variable chunks"));
+        HIPCHK(hipMemcpy(s->vchunk.p, ch.data(), ch.size() * 4, hipMemcpyHostToDevice));
+        s->n_vchunk = (int32_t)ch.size() - 1;
     }
     s->planes.release();
     s->planes_scr.release();

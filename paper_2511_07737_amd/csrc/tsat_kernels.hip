@@ -2200,11 +2200,20 @@ __global__ __launch_bounds__(256) void var_window_levels_kernel(VarArgs a)
         gt_inst = 0;
     }
     int bad = 0;
-    const uint32_t nchunks = (V + kChunk - 1) / kChunk;
+    // work items: the host's variable chunks that fill one record window
+    // (fewer windows, so fewer transposes), else four variables each
+    const uint32_t nchunks = a.vchunk ? (uint32_t)a.n_vchunk : (V + kChunk - 1) / kChunk;
 
     const ItemRange cr = xcd_items(a.xcd, nchunks, 4u, wave0 % 4u);
     for (uint32_t ch = cr.first; ch < cr.end; ch += cr.stride) {
-        const uint32_t vb = ch * kChunk, ve = vb + kChunk < V ? vb + kChunk : V;
+        uint32_t vb, ve;
+        if (a.vchunk) {
+            vb = sload(a.vchunk + ch);
+            ve = sload(a.vchunk + ch + 1);
+        } else {
+            vb = ch * kChunk;
+            ve = vb + kChunk < V ? vb + kChunk : V;
+        }
         const uint32_t rend = sload(a.cid_off + ve);
         uint32_t w = 0;
         bool loaded = false;
