@@ -97,9 +97,15 @@ def test_batch_equals_single_instance_runs(solver):
         assert np.array_equal(solver.get_logits(), thb[r]), j
 
 
-def test_graph_replay_equals_eager(solver):
-    cnfs = instances()
-    N = 32
+@pytest.mark.parametrize("kind,N", [("planted", 32), ("mixed", 64), ("structured", 128)])
+def test_graph_replay_equals_eager(solver, kind, N):
+    """Replayed iterations give the eager ones bit for bit: uniform widths
+    (one forward launch per bucket, the pair update at N = 32), a mixed-width
+    batch (the one-launch forward with the wide histogram pass, the level
+    gather with its window-filling work items) and one structured instance
+    at N = 128 (the full-row instance of the level gather)."""
+    cnfs = [gen.structured(2000, 9000, seed=8)] if kind == "structured" else instances(kind)
+    print(f"[graph] kind={kind} N={N}", flush=True)
     th, _, _ = stacked_state(cnfs, N, 500)
     solver.load_batch(cnfs)
     outs = []
