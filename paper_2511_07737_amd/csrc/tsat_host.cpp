@@ -835,16 +835,7 @@ static int32_t load_store(tsat_solver* s, Store&& st)
     s->vchunk.release();
     s->n_vchunk = 0;
     if (!s->st.cid_off.empty() && V > 0) {
-        const std::vector<uint32_t>& off = s->st.cid_off;
-        std::vector<uint32_t> ch;
-        for (size_t v = 0; v < V;) {
-            size_t e = v;
-            while (e < V && e - v < 8 && off[e + 1] - off[v] <= 64) ++e;
-            if (e == v) e = v + 1;
-            ch.push_back((uint32_t)v);
-            v = e;
-        }
-        ch.push_back((uint32_t)V);
+        const std::vector<uint32_t> ch = window_chunks(s->st.cid_off, V);
         RET(s->vchunk.alloc(ch.size() * 4, "variable chunks"));
         HIPCHK(hipMemcpy(s->vchunk.p, ch.data(), ch.size() * 4, hipMemcpyHostToDevice));
         s->n_vchunk = (int32_t)ch.size() - 1;

@@ -264,6 +264,20 @@ int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_t* lit_
     return TSAT_OK;
 }
 
+std::vector<uint32_t> window_chunks(const std::vector<uint32_t>& off, size_t V, size_t max_vars, uint32_t max_records)
+{
+    std::vector<uint32_t> ch;
+    for (size_t v = 0; v < V;) {
+        size_t e = v;
+        while (e < V && e - v < max_vars && off[e + 1] - off[v] <= max_records) ++e;
+        if (e == v) e = v + 1;
+        ch.push_back((uint32_t)v);
+        v = e;
+    }
+    ch.push_back((uint32_t)V);
+    return ch;
+}
+
 } // namespace tsat_host
 
 using namespace tsat_host;

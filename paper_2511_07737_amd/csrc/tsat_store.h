@@ -81,4 +81,11 @@ struct Store {
 int32_t build_store(int32_t n_inst, const int32_t* num_vars, const int64_t* lit_off, const int32_t* lits,
                     Store& st, bool with_occ, const StoreLimits& lim = StoreLimits());
 
+// Work items of a window gather over records with offsets off[0 .. V]:
+// the first variables of runs of consecutive variables, each run as long as
+// it holds at most max_vars variables and max_records records (a variable
+// with more records forms a run alone); the table ends with V.
+std::vector<uint32_t> window_chunks(const std::vector<uint32_t>& off, size_t V, size_t max_vars = 8,
+                                    uint32_t max_records = 64);
+
 } // namespace tsat_host

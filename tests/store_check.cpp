@@ -408,8 +408,37 @@ static void test_dimacs(const std::string& dir)
     CHECK(info.num_clauses == 3 && info.num_lits == 7 && info.max_width == 3 && info.width_count[2] == 2);
 }
 
+// work items of the window gathers: contiguous runs covering every
+// variable, each within the variable and record limits or a single
+// variable, none extendable by the next variable
+static void test_window_chunks()
+{
+    Rng r(17);
+    for (int t = 0; t < 200; ++t) {
+        const size_t V = (size_t)r.below(300);
+        std::vector<uint32_t> off(V + 1, 0);
+        for (size_t v = 0; v < V; ++v) {
+            const uint32_t k = r.below(8) == 0 ? 60 + r.below(100) : r.below(20); // some heavy variables
+            off[v + 1] = off[v] + k;
+        }
+        const size_t mv = 1 + r.below(10);
+        const uint32_t mr = 1 + r.below(90);
+        const std::vector<uint32_t> ch = window_chunks(off, V, mv, mr);
+        CHECK(!ch.empty() && ch.front() == 0 && ch.back() == (uint32_t)V);
+        for (size_t i = 0; i + 1 < ch.size(); ++i) {
+            const size_t b = ch[i], e = ch[i + 1];
+            CHECK(b < e);
+            const bool fits = e - b <= mv && off[e] - off[b] <= mr;
+            CHECK(fits || e - b == 1);
+            if (fits && e < V) CHECK(e - b == mv || off[e + 1] - off[b] > mr); // greedy: could not take v = e
+        }
+    }
+    CHECK(window_chunks(std::vector<uint32_t>{0}, 0).size() == 1);
+}
+
 int main(int argc, char** argv)
 {
+    test_window_chunks();
     const std::string dir = argc > 1 ? argv[1] : ".";
     test_random_stores();
     test_heavy_variable();
