@@ -11,13 +11,14 @@ resident in HBM before the timed region.  Prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 10]
                        [--workload large|structured|tiny] [--no-cpu-baseline]
-                       [--no-learned] [--no-ragged] [--no-stream] [--no-autotune]
-                       [--calib-copy-mib M]
+                       [--no-learned] [--no-ragged] [--no-structured] [--no-stream]
+                       [--no-autotune] [--calib-copy-mib M]
 
 Besides the timed workload the line carries the bandwidth reference kernels,
 the tiny-configuration steps-to-SAT distribution, the learned-versus-random
-start comparison, the ragged 1000-instance configuration and the FP64 oracle
-timed on the host (one thread and all threads).
+start comparison, the structured configuration, the ragged 1000-instance
+configuration and the FP64 oracle timed on the host (one thread and all
+threads).
 """
 from __future__ import annotations
 
@@ -235,6 +236,44 @@ def ragged_block(count, max_steps):
     return out
 
 
+def structured_block(steps):
+    """The structured configuration (community-structured planted CNF,
+    V = 5e5, C = 2.5e6, widths 2-12, N = 128) as a report of the default
+    run: the same measurement as --workload structured, autotuned, 10
+    warmup and `steps` timed iterations."""
+    import numpy as np
+
+    from paper_2511_07737_amd import gen, tsat
+
+    w = WORKLOADS["structured"]
+    print("[bench] structured: generating", file=sys.stderr, flush=True)
+    cnf = make_cnf(w)
+    N = w["N"]
+    s = tsat.Solver(device=0)
+    s.load(cnf)
+    s.init_batch(N, init_logits=gen.normal_logits(cnf.num_vars, N, w["init_seed"]))
+    cfg, used = s.autotune(iters=2)
+    s.step(10)
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    s.step(steps)
+    t1 = time.perf_counter()
+    s.set_timing(False)
+    kms, _ = s.get_timing()
+    launch = s.launch_config().as_dict()
+    s.close()
+    ms = 1e3 * (t1 - t0) / steps
+    sb = survey_bytes(cnf, N)
+    upd = frac_entry(sb["update"], kms[2], "var_step")
+    upd["traffic"] = measured_traffic("structured")
+    return {"workload": w["name"], "V": cnf.num_vars, "C": cnf.num_clauses, "L": cnf.num_lits, "N": N,
+            "steps": steps, "ms_per_step": round(ms, 5), "evals_per_s": cnf.num_lits * N / (ms * 1e-3),
+            "kernels_ms": {n: round(x, 5) for n, x in zip(["fwd_hist", "smin_tables", "var_step"], kms)},
+            "roofline": upd, "roofline_fwd": frac_entry(sb["fwd"], kms[0], "fwd_hist"),
+            "frac_fused_min": round(sb["step_fused_min"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch": launch, "autotune_iterations": used}
+
+
 def tiny_distribution():
     """Steps to all-SAT and to the 99% hand-off on the tiny configuration:
     32 planted 3-SAT instances V = 200, C = 800 (seeds 1..32), N = 64 with
@@ -374,6 +413,9 @@ def main():
                     help="skip the solve-quality reports: the learned-versus-random start comparison and the "
                          "tiny-configuration steps-to-SAT distribution")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged many-instance configuration")
+    ap.add_argument("--no-structured", action="store_true",
+                    help="skip the structured-configuration report of a run on another workload")
+    ap.add_argument("--structured-steps", type=int, default=500)
     ap.add_argument("--ragged-count", type=int, default=1000)
     ap.add_argument("--ragged-steps", type=int, default=3600)
     ap.add_argument("--no-stream", action="store_true", help="skip the bandwidth reference kernels")
@@ -485,6 +527,8 @@ def main():
         out["tiny"] = tiny_distribution()
         out["learned_vs_random"] = learned_vs_random()
         out["mixing"] = mixing_block()
+    if not args.no_structured and args.workload != "structured":
+        out["structured"] = structured_block(args.structured_steps)
     if not args.no_ragged:
         out["ragged"] = ragged_block(args.ragged_count, args.ragged_steps)
     if not args.no_cpu_baseline:
