@@ -73,7 +73,8 @@ struct FwdArgs {
     const Ctrl* ctrl;       // may be null
     const InstCtrl* ictrl;  // may be null
     uint32_t* planes;       // null, or [clauses][plane_P][plane_stride]: R of every clause in binary
-    int32_t plane_stride;   // dwords per plane row (2 J, J the update kernel's words per candidate row)
+    int32_t plane_stride;   // dwords per plane row (2 J, J the update kernel's words per candidate row;
+                            // 1 when a clause's two planes share one 8-byte word, N <= 32)
     int32_t plane_P;        // planes per clause (2 or 4)
     int64_t plane_base;     // global index of the bucket's first clause
     int32_t vrows;          // bits32 holds value rows only ([V][W2]); not-x is the complement
@@ -124,6 +125,9 @@ struct VarArgs {
                               // carry no header; 0: generic records
     int32_t group;            // records per scalar-load group in the pure kernel
     int32_t window;           // clause-plane gather by 64-record windows (vector loads, transposed)
+    int32_t packed;           // 1: two variables per wave (uniform widths 2 and 3, N <= 32), the
+                              // forward's two planes of a clause in one 8-byte word (plane 0 in
+                              // the low dword, plane 1 in the high one)
     int32_t xcd;              // XCD-aware order of the variable chunks
     const uint32_t* occ_off;  // [V+1] offsets into occ_data (words, or records if pure)
     const uint32_t* occ_mid;  // [V] first record of negative occurrences

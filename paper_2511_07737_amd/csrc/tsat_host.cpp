@@ -272,6 +272,16 @@ static bool plane_path(const tsat_solver* s, int32_t N)
     return s->window_gather && s->st.max_sign_rec < 65536 && levels_lds_bytes(s, row_words((N + 63) / 64)) <= 65536;
 }
 
+// Uniform widths 2 and 3 with the window gather at N <= 32: the update takes
+// two variables per wave and reads a clause's two planes as one 8-byte word,
+// so the forward writes them packed (plane stride of one dword).  The one
+// predicate sets the forward's layout and picks the update kernel.
+static bool packed_planes(const tsat_solver* s, int32_t N)
+{
+    return N <= 32 && s->rows_per_var == 1 && uniform_plane_store(s) && s->window_gather &&
+           s->st.max_sign_rec < 65536 && plane_path(s, N);
+}
+
 // Planes of R for N candidates: [clauses][P][2 J] dwords, zeroed when (re)allocated.
 // Clauses of widths 1 .. 3 come first in the global clause order and hold
 // two planes each (R <= 3); the wider ones follow with four.
@@ -406,7 +416,7 @@ static int32_t enqueue_fwd(tsat_solver* s, const uint64_t* lits, int32_t N, uint
     uint32_t* wide_planes = nullptr;
     if (with_planes) {
         base.planes = planes;
-        base.plane_stride = 2 * row_words(W);
+        base.plane_stride = packed_planes(s, N) ? 1 : 2 * row_words(W);
         wide_planes = planes + (size_t)G3 * 2 * base.plane_stride;
     }
     if (with_planes && multi_path(s, N)) {
@@ -541,6 +551,7 @@ static VarArgs var_args(tsat_solver* s, const tsat_params& p, int32_t N, int32_t
     a.group = s->pure_group;
     // the window gather keeps its counts in 16-bit halves
     a.window = s->window_gather && s->st.max_sign_rec < 65536;
+    a.packed = packed_planes(s, N);
     a.xcd = s->xcd_update;
     a.occ_off = s->occ_off.as<uint32_t>();
     a.occ_mid = s->occ_mid.as<uint32_t>();
@@ -587,6 +598,7 @@ static void batch_rows(const tsat_solver* s, VarArgs& a)
     a.occ_mid = a.cid_mid = s->lro.as<uint32_t>() + 1;
     a.var_inst = nullptr;
     a.window = 1;
+    a.packed = 0;
 }
 
 // FP64 partial rows of the heavy-variable chunks for N candidates

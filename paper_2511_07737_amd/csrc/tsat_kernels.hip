@@ -1731,8 +1731,8 @@ __device__ __forceinline__ void transpose64_n(uint64_t (&x)[E], uint32_t lane)
 // Planes of records [w, w + 64) (records at or past `end` read as zero),
 // transposed into the wave's LDS window: win[(p J + j) 64 + lane] bit r =
 // plane p, word j, candidate bit of record w + r.  Each lane writes its own
-// slots; a caller whose lanes read other lanes' slots (the two-variable
-// gather) orders the stores before those loads itself.
+// slots; a caller whose lanes read other lanes' slots orders the stores
+// before those loads itself.
 template <int J>
 __device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane, uint64_t* win)
 {
@@ -1750,6 +1750,23 @@ __device__ __forceinline__ void load_window(const VarArgs& a, uint32_t w, uint32
     transpose64_n<2 * J>(wd, lane);
 #pragma unroll
     for (int e = 0; e < 2 * J; ++e) win[e * 64 + lane] = wd[e];
+}
+
+// Packed planes (N <= 32: plane 0 of a clause in the low dword of one 8-byte
+// word, plane 1 in the high one) of records [w, w + 64) (records at or past
+// `end` read as zero), transposed into the wave's LDS window: one transpose
+// serves both planes, win[c] bit r = plane 0, candidate c of record w + r and
+// win[32 + c] bit r = plane 1, candidate c, for c < 32.
+__device__ __forceinline__ void load_window_packed(const VarArgs& a, uint32_t w, uint32_t end, uint32_t lane,
+                                                   uint64_t* win)
+{
+    const uint32_t rec = w + lane;
+    const bool ok = rec < end;
+    const uint32_t id = ok ? a.occ_cid[rec] : 0u;
+    const uint2 q = ok ? ((const uint2*)a.planes)[id] : make_uint2(0u, 0u);
+    uint64_t wd[1] = {((uint64_t)q.y << 32) | q.x};
+    transpose64_n<1>(wd, lane);
+    win[lane] = wd[0];
 }
 
 // bits [lo, hi) of a 64-bit word, 0 <= lo < hi <= 64
@@ -1859,8 +1876,10 @@ __global__ __launch_bounds__(256) void var_window_kernel(VarArgs a)
 // Window gather with two variables per wave (N <= 32, rows of one word):
 // lanes 0-31 hold the candidates of the first variable of a pair, lanes
 // 32-63 those of the second.  The pair's records are consecutive, so one
-// window loop covers both; every lane reads the transposed word of its
-// candidate (lane mod 32) and counts under its own variable's record masks.
+// window loop covers both; the forward leaves a clause's two planes packed
+// in one 8-byte word, one load and one transpose per record window; every
+// lane reads the two transposed words of its candidate (lane mod 32) and
+// counts under its own variable's record masks.
 // The per-variable work of the tail (two FP64 row sums, the divisions,
 // scalar loads, bit packing) is then shared by two rows.  Row sums stay
 // within each half in the order of var_tail, where the idle half adds only
@@ -1958,7 +1977,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void v
     const int N = a.N, Np = a.Np;
     const StepScalars c = load_scalars(a, OP);
     __shared__ float s_gt[4][K1 * 64];
-    __shared__ uint64_t s_win[4][2 * 64];
+    __shared__ uint64_t s_win[4][64];
     float* my_gt = s_gt[threadIdx.x / 64u];
     uint64_t* my_win = s_win[threadIdx.x / 64u];
     uint32_t gt_inst0 = 0xffffffffu, gt_inst1 = 0xffffffffu;
@@ -2021,9 +2040,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void v
                 if (!loaded || q - w >= 64u) {
                     w = q;
                     loaded = true;
-                    load_window<1>(a, w, rend, lane, my_win);
-                    // lanes 32-63 read the slots lanes 0-31 wrote: order the
-                    // LDS stores before those loads for the compiler and the wave
+                    load_window_packed(a, w, rend, lane, my_win);
+                    // every lane reads slots other lanes wrote: order the LDS
+                    // stores before those loads for the compiler and the wave
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -2032,7 +2051,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void v
                 const uint64_t mpa = window_bits(pa0, pam, q, qe, w), mna = window_bits(pam, pa1, q, qe, w);
                 const uint64_t mpb = window_bits(pb0, pbm, q, qe, w), mnb = window_bits(pbm, pb1, q, qe, w);
                 const uint64_t mp = h ? mpb : mpa, mn = h ? mnb : mna;
-                const uint64_t b0 = my_win[l], bb1 = my_win[64 + l];
+                const uint64_t b0 = my_win[l], bb1 = my_win[32 + l];
                 const uint64_t b01 = b0 | bb1; // R >= 1 (bb1: R >= 2)
                 cnt[0][0] += (uint32_t)__popcll(b01 & mp) + ((uint32_t)__popcll(b01 & mn) << 16);
                 cnt[1][0] += (uint32_t)__popcll(bb1 & mp) + ((uint32_t)__popcll(bb1 & mn) << 16);
@@ -3304,8 +3323,9 @@ static hipError_t launch_pair_k(const VarArgs& a, int op, int blocks, hipStream_
     return hipGetLastError();
 }
 
-// two variables per wave: window gather, rows of at most 32 candidates
-static bool pair_rows(const VarArgs& a) { return a.window && a.N <= 32 && !a.lit_rows; }
+// two variables per wave: window gather over packed planes, rows of at most
+// 32 candidates (the host sets the flag together with the forward's layout)
+static bool pair_rows(const VarArgs& a) { return a.packed != 0; }
 
 template <int J, int KW, bool FULL>
 static hipError_t launch_plane_jkf(const VarArgs& a, int op, int blocks, hipStream_t st)
