@@ -4,8 +4,10 @@ are exact, so the two give the same results bit for bit, on the step, the
 gradient and the adjoint, for every row width, with variables whose records
 span several windows, chunks that cross instance boundaries, and instances
 frozen while the others move on.  Rows of at most 32 candidates take the
-two-variables-per-wave form of the window gather (pairs that straddle
-instance boundaries, an odd last pair, one frozen variable of a pair).
+two-variables-per-wave form of the window gather, which reads a clause's two
+planes packed in one 8-byte word while the record gather reads them unpacked
+(pairs that straddle instance boundaries, an odd last pair, one frozen
+variable of a pair).
 Oracle parity of the window gather itself comes from the parity tests, where
 it is the default."""
 import numpy as np
