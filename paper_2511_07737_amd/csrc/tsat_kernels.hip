@@ -1969,7 +1969,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void v
         return;
     }
     constexpr int K1 = KW + 1;
-    constexpr uint32_t kChunk = 8; // variables (four pairs) per wave work item (measured best of 2, 4, 8, 16)
+    // variables (sixteen pairs) per wave work item: a chunk's last record
+    // window is partly used, so longer chunks waste less of the window loads
+    // (measured best of 4, 8, 16 and 32)
+    constexpr uint32_t kChunk = 32;
     const uint32_t lane = __lane_id();
     const uint32_t h = lane >> 5, l = lane & 31u;
     const uint32_t wave0 = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
