@@ -1985,8 +1985,11 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
     double ms[3];
     tsat_launch_config cur;
     RET(tsat_get_launch_config(s, &cur));
-    // forward work-unit target: only the forward kernels depend on it
-    static const int kFwd[] = {256, 512, 1024, 2048, 4096};
+    // forward work-unit target: only the forward kernels depend on it.  What
+    // counts is the clauses per thread that follow from it (a short loop
+    // leaves latency exposed, a long one spreads an XCD's resident blocks
+    // over too many rows for its L2), so large batches need large targets
+    static const int kFwd[] = {256, 512, 1024, 2048, 4096, 8192, 16384, 32768};
     double best_fwd = 1e30;
     int pick_fwd = cur.fwd_target_blocks;
     for (int f : kFwd) {
