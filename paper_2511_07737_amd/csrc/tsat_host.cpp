@@ -2007,7 +2007,9 @@ int32_t tsat_autotune(tsat_solver* s, int32_t iters, const tsat_params* p, tsat_
     cur.fwd_target_blocks = pick_fwd;
     // fused update kernel: blocks per CU, and the record grouping of
     // uniform-width stores
-    static const int kPerCu[] = {0, 8, 16, 32, 64};
+    // (a large ragged batch runs best far beyond the resident blocks: waves
+    // then take few chunks each, and the chip walks the variables in order)
+    static const int kPerCu[] = {0, 8, 16, 32, 64, 128, 256, 512, 1024};
     const bool pure = s->st.pure_k != 0;
     const bool planes_apply = s->occ_cid.p && (s->N + 63) / 64 <= 4;
     static const int kGroups[] = {1, 2, 4};

@@ -72,15 +72,15 @@ def test_autotune_picks_a_candidate_and_keeps_solving(pure):
     before = s.launch_config()
     c, used = s.autotune(iters=2)
     assert c.fwd_target_blocks in (256, 512, 1024, 2048, 4096, 8192, 16384, 32768)
-    assert c.var_blocks_per_cu in (0, 8, 16, 32, 64)
+    assert c.var_blocks_per_cu in (0, 8, 16, 32, 64, 128, 256, 512, 1024)
     # the record group only matters (and is only tuned) for uniform-width stores
     assert c.pure_group in ((1, 2, 4) if pure else (before.pure_group,))
     assert c.fwd_ms > 0 and c.var_ms > 0
     assert c.clause_planes in (0, 1)
-    # eight forward targets, then five blocks per CU with the clause planes on (uniform
+    # eight forward targets, then nine blocks per CU with the clause planes on (uniform
     # widths 2 and 3: by windows and by records; mixed: by windows) and, off,
     # with the three record groups (uniform widths only)
-    assert used == 2 * (8 + (5 * 2 + 5 * 3 if pure else 5 + 5))
+    assert used == 2 * (8 + (9 * 2 + 9 * 3 if pure else 9 + 9))
     got = s.launch_config()
     assert (got.fwd_target_blocks, got.var_blocks_per_cu, got.pure_group) == \
         (c.fwd_target_blocks, c.var_blocks_per_cu, c.pure_group)

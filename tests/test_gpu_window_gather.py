@@ -165,7 +165,7 @@ def test_autotune_tries_both_plane_gathers():
     assert c.window_gather in (0, 1) and c.clause_planes in (0, 1)
     # forward targets; blocks per CU with the planes on, by windows and by
     # records; without planes, with the three record groups
-    assert used == 2 * (8 + 5 * 2 + 5 * 3)
+    assert used == 2 * (8 + 9 * 2 + 9 * 3)
     with pytest.raises(tsat.TsatError) as e:
         s.set_launch_config(window_gather=2)
     assert e.value.code == tsat.E_ARG
