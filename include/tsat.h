@@ -547,8 +547,8 @@ int32_t tsat_set_launch_config(tsat_solver* s, const tsat_launch_config* cfg);
 
 /* Autotuner: times candidate shapes on real iterations of the current batch
  * (`iters` in [1, 64] iterations per candidate, per-kernel HIP-event timing):
- * first the forward work-unit target (256..4096), then the fused update's
- * blocks per CU (auto, 8, 16, 32, 64) with, for uniform-width stores, the
+ * first the forward work-unit target (256, 512, ..., 32768), then the fused
+ * update's blocks per CU (auto, 8, 16, ..., 1024) with, for uniform-width stores, the
  * clause-plane gather on (by windows and record by record) and off and,
  * without it, the record group (1, 2, 4), compared on forward + update
  * time; keeps the fastest and returns it in *best
