@@ -61,7 +61,7 @@ def uses_clause_planes(cnf, N, planes_on):
     return bool(planes_on) and w.size > 0 and int(w.max()) <= 15 and N <= 256
 
 
-def survey_bytes(cnf, N):
+def model_bytes(cnf, N):
     """Algorithmic bytes of the path's byte model (per iteration):
     - update: clause indices (4 B per literal), the current value rows
       (V N / 8), theta, m, v read and written (24 B per (variable,
@@ -263,7 +263,7 @@ def structured_block(steps):
     launch = s.launch_config().as_dict()
     s.close()
     ms = 1e3 * (t1 - t0) / steps
-    sb = survey_bytes(cnf, N)
+    sb = model_bytes(cnf, N)
     upd = frac_entry(sb["update"], kms[2], "var_step")
     upd["traffic"] = measured_traffic("structured")
     return {"workload": w["name"], "V": cnf.num_vars, "C": cnf.num_clauses, "L": cnf.num_lits, "N": N,
@@ -459,7 +459,7 @@ def main():
     value = evals_per_step * args.steps / sec
 
     planes = uses_clause_planes(cnf, N, s.launch_config().clause_planes)
-    sb = survey_bytes(cnf, N)
+    sb = model_bytes(cnf, N)
     impl = implementation_bytes(cnf, N, planes)
     names = ["fwd_hist", "smin_tables", "var_step"]
     dom = int(np.argmax(kms))

@@ -27,7 +27,7 @@ def test_threaded_oracle_step_equals_oracle_step():
 def test_byte_models():
     cnf = gen.planted_ksat(1000, 4100, 3, seed=1)
     N = 256
-    sb = bench.survey_bytes(cnf, N)
+    sb = bench.model_bytes(cnf, N)
     V, L = 1000, cnf.num_lits
     assert sb["fwd"] == 4 * L + V * N / 8
     assert sb["update"] == 4 * L + 2 * V * N / 8 + 24 * V * N
