@@ -50,8 +50,8 @@ def assert_same(a, b):
             assert np.array_equal(wa[0], wb[0]) and wa[1] == wb[1]
 
 
-@pytest.mark.parametrize("k,N", [(3, 256), (3, 200), (3, 100), (3, 64), (3, 17), (3, 1), (2, 256), (2, 64),
-                                 (2, 9)])
+@pytest.mark.parametrize("k,N", [(3, 256), (3, 200), (3, 100), (3, 64), (3, 33), (3, 32), (3, 17), (3, 1),
+                                 (2, 256), (2, 64), (2, 9)])
 def test_window_gather_equals_record_gather(k, N):
     V = 1001
     cnf = gen.planted_ksat(V, int((4.0 if k == 3 else 1.5) * V), k, seed=40 + k)
